@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the planted (l, d) motif search on one MI355X.
+
+Default: the (15,4) FM workload (n=20, t=600, seed 0), inputs resident in HBM.
+One step = one whole solve through the device-level C ABI on torch's current
+stream: window building (a1-a2), the persistent search (a3-a6), then the
+motif count and codes copied back and sorted on the host (a7).  Prints one
+JSON line.  ``--mode batched`` / ``--mode serving`` print the batched and
+serving lines instead.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# gfx950: 256 compute units x 4 SIMD x 16 lanes, 2.4 GHz peak engine clock.
+CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
+VALU_INT32_PEAK = CUS * LANES_PER_CU * CLOCK_HZ          # lane-ops/s
+# VALU instructions per window compare in the search kernel's inner loop:
+# v_xor_b32, v_or_b32_sdwa, v_bcnt_u32_b32 and half of a v_min3_u32.
+OPS_PER_COMPARE = 3.5
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving"])
+    ap.add_argument("--config", default="plain_15_4", choices=["plain_8_1", "plain_11_3", "plain_15_4"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target length of the oracle CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="HBM bytes per launch measured by rocprofv3 counters")
+    return ap.parse_args()
+
+
+def cpu_baseline(seqs, l, d, target_s):
+    """The oracle (brute mode, unmodified) on a bounded prefix of the candidate space."""
+    import oracle
+    threads = os.cpu_count() or 1
+    span = 1 << 14
+    while True:
+        t0 = time.perf_counter()
+        oracle.solve(seqs, l, d, mode="brute", threads=threads, k_range=(0, span))
+        dt = time.perf_counter() - t0
+        if dt >= target_s / 4 or span >= 4 ** l:
+            break
+        span = min(4 ** l, int(span * max(2.0, min(16.0, target_s / 4 / max(dt, 1e-3)))))
+    if dt < target_s / 2 and span < 4 ** l:
+        span = min(4 ** l, int(span * target_s / dt))
+        t0 = time.perf_counter()
+        oracle.solve(seqs, l, d, mode="brute", threads=threads, k_range=(0, span))
+        dt = time.perf_counter() - t0
+    return {"value": span / dt, "unit": "candidates/s", "cores": threads, "kind": "oracle",
+            "sample": f"brute-mode oracle over candidates [0, {span}) of the same instance "
+                      f"({span / 4 ** l:.2e} of 4^{l}), {dt:.1f} s on {threads} host threads"}
+
+
+def load_traffic(path, key):
+    try:
+        with open(path) as f:
+            return json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def bench_plain(args):
+    import torch
+    import fmgen
+    from paper_1403_1313_amd import native as nat
+
+    shape = fmgen.PLAIN[args.config]
+    inst = fmgen.gen_fm(seed=args.seed, **shape)
+    l, d, n, t = inst.l, inst.d, inst.n, inst.t
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    seqs = torch.from_numpy(inst.seqs.reshape(-1).copy()).to(dev)
+    cap = 1 << 20
+    out = torch.zeros(cap, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    host_cnt = torch.zeros(1, dtype=torch.int64).pin_memory()
+
+    def step():
+        nat.solve_dev(seqs, n, t, l, d, out, cap, cnt, stream=stream)
+        host_cnt.copy_(cnt, non_blocking=True)
+        stream.synchronize()
+        k = min(int(host_cnt.item()), cap)
+        codes = np.sort(out[:k].cpu().numpy().view(np.uint32))
+        return codes, nat.last_stats()
+
+    for _ in range(args.warmup):
+        codes, st = step()
+    torch.cuda.synchronize()
+    kernel_ms, windows_ms = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        codes, st = step()
+        kernel_ms.append(st["kernel_ms"])
+        windows_ms.append(st["windows_ms"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    cands = 4 ** l
+    k_ms = float(np.mean(kernel_ms))
+    wc = st["window_compares"]
+    achieved = wc * OPS_PER_COMPARE / (k_ms * 1e-3)
+
+    parity = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"{args.config}.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            recs = [r for r in json.load(f)["records"] if r["seed"] == args.seed]
+        if recs:
+            parity = [nat.decode(int(c), l) for c in codes] == recs[0]["motifs"] and \
+                st["seq_visits"] == recs[0]["skip_visits"]
+
+    traffic = load_traffic(args.traffic, f"pms_search_kernel/{args.config}")
+    line = {
+        "metric": "candidates/s",
+        "value": cands / (ms_step * 1e-3),
+        "unit": "candidates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"FM planted ({l},{d}) motif search, n={n}, t={t}, seed {args.seed}, "
+                               f"all 4^{l} candidates", "l": l, "d": d, "n": n, "t": t,
+                   "seed": args.seed, "candidates": cands},
+        "window_compares_per_s": wc / (ms_step * 1e-3),
+        "kernel_ms": k_ms,
+        "windows_kernel_ms": float(np.mean(windows_ms)),
+        "wall_ms_per_step": wall * 1e3 / args.steps,
+        "seq_visits": st["seq_visits"],
+        "window_compares": wc,
+        "executed_lane_scans": st["batches"] * 64,
+        "lane_efficiency": st["seq_visits"] / max(1, st["batches"] * 64),
+        "motifs": int(codes.size),
+        "parity_vs_golden": parity,
+        "launch": {"grid": st["grid"], "wg_waves": st["wg_waves"], "chunk": st["chunk"]},
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": VALU_INT32_PEAK / 1e12,
+            "unit": "Tops/s",
+            "frac": achieved / VALU_INT32_PEAK,
+            "traffic": traffic,
+            "kernel": "pms_search_kernel",
+            "ops_per_compare": OPS_PER_COMPARE,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(inst.seqs, l, d, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the search shards "
+              "by candidate ranges across GPUs, which this build does not launch.", file=sys.stderr)
+        return 2
+    if args.mode == "plain":
+        return bench_plain(args)
+    if args.mode == "batched":
+        from paper_1403_1313_amd import benchmarks
+        return benchmarks.bench_batched(args)
+    from paper_1403_1313_amd import benchmarks
+    return benchmarks.bench_serving(args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

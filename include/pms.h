@@ -1,0 +1,242 @@
+/*
+ * pms.h -- exact planted (l, d) motif search (Skip-Brute-Force) on one
+ * AMD Instinct MI355X (gfx950).  C ABI: plain pointers and sizes.
+ *
+ * The operation (Section I.A, the planted (l, d) motif problem; Section
+ * III.A, the enhanced brute force): given n DNA sequences of length t, the
+ * result is every l-mer x over {A, C, G, T} such that every sequence has a
+ * window (a length-l substring at any start 0 .. t-l, t-l+1 of them) within
+ * Hamming distance d of x.  All 4^l l-mers are candidates; a candidate is
+ * rejected at the first sequence that has no such window, and the remaining
+ * sequences are not examined (the enhanced rule of Section III.A).  The
+ * candidate space is split into numbered index ranges that workers claim and
+ * generate on the fly (Section IV.A).
+ *
+ * Motif code: base p of the l-mer (p = 0 leftmost) occupies bits
+ * [2(l-1-p), 2(l-1-p)+1], with A=0, C=1, G=2, T=3.  Ascending codes are the
+ * dictionary order of the strings (A < C < G < T).  Codes fit in uint32
+ * because l <= 16.
+ *
+ * Threading: every entry point may be called from several host threads; the
+ * host-level calls serialise on one library lock per device.  Device-level
+ * calls are asynchronous on the caller's stream.
+ *
+ * Errors: no entry point aborts or throws.  Each returns a pms_status; on a
+ * non-OK status pms_last_error() returns a message for the calling thread.
+ */
+#ifndef PMS_H
+#define PMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every entry point. */
+enum pms_status {
+    PMS_OK = 0,
+    PMS_ERR_INVALID = 1,  /* bad argument; nothing was written except *count = 0 */
+    PMS_ERR_OVERFLOW = 2, /* more motifs than capacity; see each entry point */
+    PMS_ERR_NOMEM = 3,    /* device or pinned host memory could not be allocated */
+    PMS_ERR_DEVICE = 4    /* a HIP runtime call failed; detail in pms_last_error() */
+};
+
+/* Limits checked by every entry point (PMS_ERR_INVALID beyond them).
+ * l: codes are 32-bit.  n: per-wavefront stage bookkeeping holds one stage
+ * per lane of a 64-wide wavefront.  t: one row, packed 16 bases per word,
+ * is staged in the LDS of one workgroup. */
+#define PMS_MAX_L 16
+#define PMS_MAX_N 64
+#define PMS_MAX_T (1 << 17)
+
+/*
+ * pms_solve -- one instance, host buffers in and out, synchronous.
+ *
+ *   seqs        n pointers, each to at least t bytes of A/C/G/T (either
+ *               case); no terminator needed.  Read only; nothing retained.
+ *   n, t, l, d  1 <= n <= PMS_MAX_N, 1 <= l <= PMS_MAX_L, l <= t <= PMS_MAX_T,
+ *               0 <= d <= l.
+ *   out_motifs  caller-owned array of *out_count (on entry) uint32 slots; may
+ *               be NULL only when *out_count == 0 on entry.
+ *   out_count   in: capacity of out_motifs.  out: |M|, the exact number of
+ *               motifs (also on PMS_ERR_OVERFLOW; 0 on PMS_ERR_INVALID).
+ *
+ * On PMS_OK out_motifs[0 .. |M|) holds M ascending, without duplicates.
+ * If |M| exceeds the capacity the smallest `capacity` motifs are written,
+ * ascending, and PMS_ERR_OVERFLOW is returned; capacity 0 is a size query.
+ * PMS_ERR_INVALID (NULL pointer, size out of range, a byte that is not a
+ * base) writes nothing to out_motifs.
+ */
+int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t d,
+              uint32_t* out_motifs, uint64_t* out_count);
+
+/* One instance of a batched solve (host buffers). */
+typedef struct {
+    const char* const* seqs; /* n pointers to >= t bytes each, as for pms_solve */
+    int32_t n, t, l, d;
+    uint32_t* out_motifs;    /* caller-owned, `capacity` slots; NULL iff capacity 0 */
+    uint64_t capacity;
+} pms_instance;
+
+/* Per-instance outcome of a batched solve. */
+typedef struct {
+    int32_t status;    /* pms_status of this instance */
+    int32_t reserved;
+    uint64_t count;    /* |M| (exact, also on PMS_ERR_OVERFLOW) */
+    double latency_ms; /* device time from the launch's first claim to this
+                          instance's last work item retiring */
+} pms_result;
+
+/*
+ * pms_solve_many -- many independent instances of uneven (l, d, n, t) in one
+ * persistent launch (replayed from a captured HIP graph when the batch has
+ * the same layout as the previous call).  Same per-instance semantics as
+ * pms_solve.  An invalid instance gets PMS_ERR_INVALID and does not stop the
+ * others.  Returns PMS_OK when every instance is OK, else the first non-OK
+ * instance status (PMS_ERR_INVALID for bad `inst`/`count`/`results`).
+ */
+int pms_solve_many(const pms_instance* inst, int32_t count, pms_result* results);
+
+/* Writes the l characters of motif `code` to out (no terminator). */
+void pms_decode(uint32_t code, int32_t l, char* out);
+
+/* Static text for a status code. */
+const char* pms_status_string(int status);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char* pms_last_error(void);
+
+/* ------------------------------------------------------------------------ *
+ * Launch configuration and tuning
+ * ------------------------------------------------------------------------ */
+
+/* Shape of the persistent search launch.  Zero fields mean "default". */
+typedef struct {
+    uint32_t chunk;        /* candidates per work item (multiple of 64) */
+    uint32_t wg_waves;     /* 64-lane wavefronts per workgroup (1..16) */
+    uint32_t wgs_per_cu;   /* resident workgroups per compute unit (0 = as many as fit) */
+    uint32_t tail_split;   /* work items of the last tail_split/64 of each instance are
+                              cut 4x smaller, so the launch ends evenly (0..64) */
+} pms_config;
+
+/* Sets the configuration used by later calls that pass no configuration
+ * (NULL restores the defaults).  PMS_ERR_INVALID for out-of-range fields. */
+int pms_set_config(const pms_config* cfg);
+int pms_get_config(pms_config* cfg);
+
+/*
+ * pms_autotune -- times the candidate-chunk x workgroup-shape grid on one
+ * instance shape (FM synthetic data drawn inside the library from a fixed
+ * seed) and makes the fastest the current configuration.  The result is
+ * cached in the JSON file named by cache_path (or $PMS_AUTOTUNE_CACHE when
+ * cache_path is NULL; no caching when both are absent), keyed by GPU
+ * architecture, compute-unit count and shape bucket.  best may be NULL.
+ */
+int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_path,
+                 pms_config* best);
+
+/* Counters of the last host-level solve on this device (or of the last
+ * pms_solve_dev / pms_step_launch whose stream has been synchronised). */
+typedef struct {
+    double kernel_ms;        /* search kernel, HIP events on its own stream */
+    double windows_ms;       /* window-building kernel, HIP events */
+    uint64_t seq_visits;     /* (candidate, sequence) scans = algorithmic work of the
+                                enhanced rule; times the window count it is the
+                                algorithmic window-compare count */
+    uint64_t batches;        /* 64-lane sequence scans executed */
+    uint64_t window_compares;/* sum over instances of seq_visits x (t-l+1) */
+    uint32_t grid;           /* workgroups launched */
+    uint32_t wg_waves;
+    uint32_t chunk;
+    uint32_t reruns;         /* relaunches caused by device output overflow */
+} pms_stats;
+
+int pms_last_stats(pms_stats* out);
+
+/* ------------------------------------------------------------------------ *
+ * Device level: device pointers, caller's stream (hipStream_t as void*; NULL
+ * is the null stream).  Asynchronous: results are valid once the stream is
+ * synchronised.  The caller owns every buffer passed in.
+ * ------------------------------------------------------------------------ */
+
+/* Number of uint32 window slots per sequence row for length t and motif
+ * length l: t-l+1 rounded up to a multiple of 16 (0 for invalid sizes). */
+int32_t pms_window_stride(int32_t t, int32_t l);
+
+/*
+ * pms_build_windows -- steps a1+a2: encodes n rows of t bytes (row-major at
+ * dev_seqs, device memory) into 2-bit codes, stages each row in LDS, and
+ * writes every window of length l in bit-plane form to
+ * dev_windows[n][pms_window_stride(t, l)] (high-bit plane of base p in bit
+ * 16 + l-1-p, low-bit plane in bit l-1-p; padding slots repeat window 0).
+ * Bytes that are not A/C/G/T (either case) set *dev_bad (device uint32) to 1;
+ * dev_bad may be NULL.
+ */
+int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l,
+                      uint32_t* dev_windows, uint32_t* dev_bad, void* stream);
+
+/* Device-resident description of one instance for pms_step_launch. */
+typedef struct {
+    const uint32_t* windows; /* [n][nw_stride] from pms_build_windows */
+    uint32_t* out;           /* motif codes, unsorted, up to out_cap of them */
+    uint64_t out_cap;
+    int32_t n, nw_stride, l, d;
+} pms_dev_instance;
+
+/* One work item: candidates [begin, begin+len) of instance `inst`, numbered
+ * in bit-plane order (candidate k has high plane k >> l and low plane
+ * k & (2^l - 1)).  len is at most 2^31. */
+typedef struct {
+    uint64_t begin;
+    uint32_t len;
+    uint32_t inst;
+} pms_work_item;
+
+/* Per-instance device state.  Before a launch: count = visits = t_done = 0
+ * and items_left = number of work items of the instance in the launch. */
+typedef struct {
+    uint64_t count;      /* motifs found (keeps counting past out_cap) */
+    uint64_t visits;     /* (candidate, sequence) scans */
+    uint64_t t_done;     /* device realtime stamp (100 MHz) when items_left hit 0 */
+    uint32_t items_left;
+    uint32_t reserved;
+} pms_dev_state;
+
+/* Launch-wide device counters; all zero before a launch. */
+typedef struct {
+    uint32_t next_item;  /* work-claim counter */
+    uint32_t error;      /* set to 1 if an instance had n > max_n (its items are skipped) */
+    uint64_t batches;    /* 64-lane sequence scans executed */
+    uint64_t t_start;    /* realtime stamp of the first claim */
+} pms_dev_counters;
+
+/*
+ * pms_step_launch -- steps a3-a6: one persistent search launch over the
+ * work items dev_work[0 .. n_work).  Each instance's survivors are appended
+ * (unsorted, as motif codes) to its `out`; its state counts them.  cfg may be
+ * NULL (current configuration).  n_inst/n_work are the table lengths;
+ * max_n is the largest n over the instances (it sizes LDS).
+ */
+int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32_t max_n,
+                    const pms_work_item* dev_work, int32_t n_work,
+                    pms_dev_state* dev_state, pms_dev_counters* dev_counters,
+                    const pms_config* cfg, void* stream);
+
+/*
+ * pms_solve_dev -- the whole device part of one solve on the caller's stream:
+ * builds windows, lays out work items, and runs the search.  dev_seqs holds
+ * n*t bytes row-major on the device.  Motif codes are appended, unsorted, to
+ * dev_out (capacity `capacity`); *dev_count (device uint64) receives |M|
+ * (exact, also when it exceeds capacity).  Workspace is owned by the library
+ * and reused; the call is asynchronous.  Invalid bytes are not checked
+ * here (use pms_build_windows's flag or the host-level calls).
+ */
+int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
+                  uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMS_H */

@@ -1,0 +1,989 @@
+// pms_api.hip -- host side of the C ABI declared in include/pms.h.
+//
+// One context per device holds the stream, the workspace (device buffers and
+// pinned host mirrors that only grow), the current launch configuration, the
+// captured graph of the last batched layout, and the counters of the last
+// solve.  Host-level calls take the context lock; nothing is retained from
+// the caller's buffers after a call returns.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <fstream>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "pms.h"
+#include "pms_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+#define PMS_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? PMS_ERR_NOMEM : PMS_ERR_DEVICE,       \
+                        std::string(#call) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+#define PMS_TRY(expr)                 \
+    do {                              \
+        int s_ = (expr);              \
+        if (s_ != PMS_OK) return s_;  \
+    } while (0)
+
+// Forced failure for tests of error propagation: PMS_TEST_FAIL_NEXT=<status>
+// makes the next host-level call return that status (the variable is then
+// cleared).  Checked before any device work.
+int test_hook() {
+    const char* v = getenv("PMS_TEST_FAIL_NEXT");
+    if (!v || !*v) return PMS_OK;
+    const int s = atoi(v);
+    unsetenv("PMS_TEST_FAIL_NEXT");
+    if (s <= PMS_OK || s > PMS_ERR_DEVICE) return PMS_OK;
+    return fail(s, "failure injected by PMS_TEST_FAIL_NEXT");
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Buffers that only grow.
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return PMS_OK;
+        size_t want = std::max(bytes, cap + cap / 2);
+        want = align_up(want, 1 << 16);
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            cap = 0;
+        }
+        PMS_HIP(hipMalloc(&p, want));
+        cap = want;
+        return PMS_OK;
+    }
+    template <typename T>
+    T* as(size_t byte_off = 0) const { return reinterpret_cast<T*>(static_cast<char*>(p) + byte_off); }
+};
+
+struct HostBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return PMS_OK;
+        size_t want = align_up(std::max(bytes, cap + cap / 2), 1 << 16);
+        if (p) {
+            (void)hipHostFree(p);
+            p = nullptr;
+            cap = 0;
+        }
+        PMS_HIP(hipHostMalloc(&p, want, hipHostMallocDefault));
+        cap = want;
+        return PMS_OK;
+    }
+    template <typename T>
+    T* as(size_t byte_off = 0) const { return reinterpret_cast<T*>(static_cast<char*>(p) + byte_off); }
+};
+
+// ---------------------------------------------------------------------------
+// Configuration.
+// ---------------------------------------------------------------------------
+pms_config default_config() {
+    pms_config c;
+    c.chunk = 1u << 14;
+    c.wg_waves = 4;
+    c.wgs_per_cu = 0;
+    c.tail_split = 8;
+    return c;
+}
+
+bool config_ok(const pms_config& c) {
+    return c.chunk >= 64 && c.chunk % 64 == 0 && c.chunk <= (1u << 24) && c.wg_waves >= 1 &&
+           c.wg_waves <= 16 && c.wgs_per_cu <= 64 && c.tail_split <= 64;
+}
+
+pms_config resolve(const pms_config* c, const pms_config& cur) {
+    if (!c) return cur;
+    pms_config r = *c;
+    const pms_config dflt = default_config();
+    if (r.chunk == 0) r.chunk = dflt.chunk;
+    if (r.wg_waves == 0) r.wg_waves = dflt.wg_waves;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Per-instance planning.
+// ---------------------------------------------------------------------------
+struct Shape {
+    int32_t n, t, l, d;
+};
+
+int validate_shape(int32_t n, int32_t t, int32_t l, int32_t d) {
+    if (n < 1 || n > PMS_MAX_N) return fail(PMS_ERR_INVALID, "n out of range [1, 64]");
+    if (l < 1 || l > PMS_MAX_L) return fail(PMS_ERR_INVALID, "l out of range [1, 16]");
+    if (t < l || t > PMS_MAX_T) return fail(PMS_ERR_INVALID, "t out of range [l, 2^17]");
+    if (d < 0 || d > l) return fail(PMS_ERR_INVALID, "d out of range [0, l]");
+    return PMS_OK;
+}
+
+int validate_rows(const char* const* seqs, int32_t n, int32_t t) {
+    if (!seqs) return fail(PMS_ERR_INVALID, "seqs is NULL");
+    for (int32_t i = 0; i < n; ++i) {
+        const char* r = seqs[i];
+        if (!r) return fail(PMS_ERR_INVALID, "seqs[" + std::to_string(i) + "] is NULL");
+        for (int32_t j = 0; j < t; ++j) {
+            const unsigned c = static_cast<unsigned char>(r[j]) | 0x20u;
+            if (c != 'a' && c != 'c' && c != 'g' && c != 't')
+                return fail(PMS_ERR_INVALID, "byte " + std::to_string(j) + " of sequence " +
+                                                 std::to_string(i) + " is not A/C/G/T");
+        }
+    }
+    return PMS_OK;
+}
+
+int32_t window_stride(int32_t t, int32_t l) {
+    if (l < 1 || t < l) return 0;
+    return static_cast<int32_t>(align_up(static_cast<size_t>(t - l + 1), 16));
+}
+
+// Probability that a uniform random window lies within d of a fixed l-mer,
+// and the expected survivors / sequence scans under independent uniform
+// background.  Used only to size buffers and order work.
+struct Estimate {
+    double motifs;      // expected |M|
+    double visits;      // expected sequence scans per candidate
+};
+
+Estimate estimate(const Shape& s) {
+    double ball = 0, binom = 1;
+    for (int k = 0; k <= s.d; ++k) {
+        if (k > 0) binom = binom * (s.l - k + 1) / k;
+        ball += binom * std::pow(3.0, k);
+    }
+    const double cands = std::ldexp(1.0, 2 * s.l);
+    const double p = ball / cands;
+    const double nw = s.t - s.l + 1;
+    const double ps = 1.0 - std::pow(1.0 - p, nw);
+    double ev = 0, pk = 1;
+    for (int k = 0; k < s.n; ++k) {
+        ev += pk;
+        pk *= ps;
+    }
+    return {cands * pk + 1.0, ev};
+}
+
+// Device output slots reserved for one instance before its count is known.
+// PMS_TEST_DEVICE_CAP=<k> caps the reservation (tests of the rerun path).
+uint64_t output_capacity(const Shape& s) {
+    const double cands = std::ldexp(1.0, 2 * s.l);
+    const double e = estimate(s).motifs;
+    uint64_t want = static_cast<uint64_t>(std::min(cands, 8.0 * e + 4096.0));
+    if (const char* v = getenv("PMS_TEST_DEVICE_CAP")) {
+        const long long k = atoll(v);
+        if (k > 0 && static_cast<uint64_t>(k) < want) want = static_cast<uint64_t>(k);
+    }
+    return want;
+}
+
+// ---------------------------------------------------------------------------
+// Device context.
+// ---------------------------------------------------------------------------
+struct Batch {
+    // host-side description of one launch
+    std::vector<Shape> shape;
+    std::vector<const char* const*> rows;
+    std::vector<size_t> raw_off, win_off, out_off;
+    std::vector<uint64_t> out_cap;
+    std::vector<pms_win_job> jobs;
+    std::vector<pms_work_item> work;
+    std::vector<uint32_t> items_per_inst;
+    size_t raw_bytes = 0, win_words = 0, out_words = 0;
+    int32_t max_n = 1, max_t = 1;
+    // meta layout (bytes) inside d_meta / h_meta
+    size_t off_insts = 0, off_jobs = 0, off_work = 0, off_state = 0, off_ctr = 0, off_bad = 0,
+           meta_bytes = 0;
+};
+
+struct Ctx {
+    std::mutex mu;
+    bool ready = false;
+    int device = 0;
+    int cus = 0;
+    size_t lds_per_block = 65536;
+    std::string arch;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    DevBuf d_raw, d_win, d_out, d_meta;
+    HostBuf h_raw, h_meta, h_back;
+    pms_config cfg = default_config();
+    pms_stats last{};
+    bool last_pending = false;     // last stats still need the event times
+    hipStream_t last_stream = nullptr;
+    // graph cache
+    hipGraphExec_t gexec = nullptr;
+    std::string gsig;
+    // device-level workspace for pms_solve_dev
+    DevBuf dv_win, dv_meta;
+    HostBuf hv_meta;
+    hipEvent_t dv_copied = nullptr;
+    bool dv_copy_live = false;
+    // where the last pms_solve_dev left its state and counters (0 = none)
+    size_t dv_state_off = 0, dv_ctr_off = 0;
+    int32_t dv_nw = 0;
+    bool dv_counters = false;
+};
+
+Ctx g_ctx;
+
+int init_ctx(Ctx& c) {
+    if (c.ready) return PMS_OK;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0)
+        return fail(PMS_ERR_DEVICE, "no HIP device available");
+    int dev = 0;
+    if (const char* v = getenv("PMS_DEVICE")) dev = atoi(v);
+    else (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= count) return fail(PMS_ERR_DEVICE, "PMS_DEVICE out of range");
+    PMS_HIP(hipSetDevice(dev));
+    hipDeviceProp_t prop;
+    PMS_HIP(hipGetDeviceProperties(&prop, dev));
+    c.device = dev;
+    c.cus = prop.multiProcessorCount;
+    c.lds_per_block = prop.sharedMemPerBlock;
+    c.arch = prop.gcnArchName;
+    PMS_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    for (auto& e2 : c.ev) PMS_HIP(hipEventCreate(&e2));
+    PMS_HIP(hipEventCreateWithFlags(&c.dv_copied, hipEventDisableTiming));
+    c.ready = true;
+    return PMS_OK;
+}
+
+// Workgroup shape and grid for a search launch.
+int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t* grid,
+                 uint32_t* waves, uint32_t* q_words) {
+    const uint32_t qw = pms::queue_words(max_n);
+    const size_t per_wave = static_cast<size_t>(qw + PMS_OUTBUF) * sizeof(uint32_t);
+    uint32_t w = cfg.wg_waves;
+    while (w > 1 && per_wave * w > c.lds_per_block) --w;
+    if (per_wave * w > c.lds_per_block)
+        return fail(PMS_ERR_INVALID, "stage queues exceed the LDS of one workgroup");
+    int per_cu = 0;
+    PMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(pms::search_kernel_symbol()), 64 * w, per_wave * w));
+    if (per_cu < 1) per_cu = 1;
+    if (cfg.wgs_per_cu > 0 && static_cast<int>(cfg.wgs_per_cu) < per_cu) per_cu = cfg.wgs_per_cu;
+    *grid = static_cast<uint32_t>(per_cu * c.cus);
+    *waves = w;
+    *q_words = qw;
+    return PMS_OK;
+}
+
+// Cuts each instance's candidate range into work items.  Instances go in
+// descending order of estimated work (longest first); inside an instance the
+// last tail_split/64 of the range uses items a quarter of `chunk`, so the
+// launch ends with small items.
+void build_work(Batch& b, const std::vector<int>& order, const pms_config& cfg) {
+    b.work.clear();
+    b.items_per_inst.assign(b.shape.size(), 0);
+    for (int i : order) {
+        const Shape& s = b.shape[i];
+        const uint64_t total = 1ull << (2 * s.l);
+        const uint64_t tail = total * cfg.tail_split / 64;
+        const uint64_t head_end = total - tail;
+        const uint64_t small = std::max<uint64_t>(64, cfg.chunk / 4);
+        uint64_t k = 0;
+        while (k < total) {
+            const uint64_t step = k < head_end ? cfg.chunk : small;
+            const uint64_t len = std::min<uint64_t>(step, total - k);
+            b.work.push_back({k, static_cast<uint32_t>(len), static_cast<uint32_t>(i)});
+            b.items_per_inst[i]++;
+            k += len;
+        }
+    }
+}
+
+// Lays out raw bytes, windows, outputs and the meta block for the instances.
+void plan_batch(Batch& b, const pms_config& cfg) {
+    const size_t m = b.shape.size();
+    b.raw_off.resize(m);
+    b.win_off.resize(m);
+    b.out_off.resize(m);
+    b.out_cap.resize(m);
+    b.jobs.clear();
+    b.raw_bytes = b.win_words = b.out_words = 0;
+    b.max_n = 1;
+    b.max_t = 1;
+    std::vector<double> cost(m);
+    for (size_t i = 0; i < m; ++i) {
+        const Shape& s = b.shape[i];
+        const int32_t stride = window_stride(s.t, s.l);
+        b.raw_off[i] = b.raw_bytes;
+        b.win_off[i] = b.win_words;
+        b.out_off[i] = b.out_words;
+        if (b.out_cap[i] == 0) b.out_cap[i] = output_capacity(s);
+        for (int32_t r = 0; r < s.n; ++r)
+            b.jobs.push_back({b.raw_off[i] + static_cast<size_t>(r) * s.t,
+                              b.win_off[i] + static_cast<size_t>(r) * stride, s.t, s.l, stride,
+                              static_cast<int32_t>(i)});
+        b.raw_bytes += align_up(static_cast<size_t>(s.n) * s.t, 256);
+        b.win_words += static_cast<size_t>(s.n) * stride;
+        b.out_words += align_up(b.out_cap[i], 64);
+        b.max_n = std::max(b.max_n, s.n);
+        b.max_t = std::max(b.max_t, s.t);
+        cost[i] = std::ldexp(1.0, 2 * s.l) * (s.t - s.l + 1) * estimate(s).visits;
+    }
+    std::vector<int> order(m);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    build_work(b, order, cfg);
+    size_t off = 0;
+    b.off_insts = off;
+    off = align_up(off + m * sizeof(pms_dev_instance), 256);
+    b.off_jobs = off;
+    off = align_up(off + b.jobs.size() * sizeof(pms_win_job), 256);
+    b.off_work = off;
+    off = align_up(off + b.work.size() * sizeof(pms_work_item), 256);
+    b.off_state = off;
+    off = align_up(off + m * sizeof(pms_dev_state), 256);
+    b.off_ctr = off;
+    off = align_up(off + sizeof(pms_dev_counters), 256);
+    b.off_bad = off;
+    off = align_up(off + m * sizeof(uint32_t), 256);
+    b.meta_bytes = off;
+}
+
+// Fills the pinned staging buffers for a planned batch.
+int stage_batch(Ctx& c, Batch& b) {
+    PMS_TRY(c.d_raw.ensure(std::max<size_t>(b.raw_bytes, 256)));
+    PMS_TRY(c.d_win.ensure(std::max<size_t>(b.win_words * 4, 256)));
+    PMS_TRY(c.d_out.ensure(std::max<size_t>(b.out_words * 4, 256)));
+    PMS_TRY(c.d_meta.ensure(b.meta_bytes));
+    PMS_TRY(c.h_raw.ensure(std::max<size_t>(b.raw_bytes, 256)));
+    PMS_TRY(c.h_meta.ensure(b.meta_bytes));
+    PMS_TRY(c.h_back.ensure(b.meta_bytes));
+    const size_t m = b.shape.size();
+    for (size_t i = 0; i < m; ++i) {
+        const Shape& s = b.shape[i];
+        char* dst = c.h_raw.as<char>(b.raw_off[i]);
+        for (int32_t r = 0; r < s.n; ++r) memcpy(dst + static_cast<size_t>(r) * s.t, b.rows[i][r], s.t);
+    }
+    memset(c.h_meta.p, 0, b.meta_bytes);
+    pms_dev_instance* insts = c.h_meta.as<pms_dev_instance>(b.off_insts);
+    pms_dev_state* state = c.h_meta.as<pms_dev_state>(b.off_state);
+    for (size_t i = 0; i < m; ++i) {
+        const Shape& s = b.shape[i];
+        insts[i].windows = c.d_win.as<uint32_t>() + b.win_off[i];
+        insts[i].out = c.d_out.as<uint32_t>() + b.out_off[i];
+        insts[i].out_cap = b.out_cap[i];
+        insts[i].n = s.n;
+        insts[i].nw_stride = window_stride(s.t, s.l);
+        insts[i].l = s.l;
+        insts[i].d = s.d;
+        state[i].items_left = b.items_per_inst[i];
+    }
+    memcpy(c.h_meta.as<char>(b.off_jobs), b.jobs.data(), b.jobs.size() * sizeof(pms_win_job));
+    memcpy(c.h_meta.as<char>(b.off_work), b.work.data(), b.work.size() * sizeof(pms_work_item));
+    return PMS_OK;
+}
+
+// Enqueues copy-in, both kernels and copy-back of the state block on c.stream.
+int enqueue_batch(Ctx& c, const Batch& b, bool timed, uint32_t grid, uint32_t waves,
+                  uint32_t qw) {
+    char* dm = c.d_meta.as<char>();
+    PMS_HIP(hipMemcpyAsync(c.d_raw.p, c.h_raw.p, b.raw_bytes, hipMemcpyHostToDevice, c.stream));
+    PMS_HIP(hipMemcpyAsync(dm, c.h_meta.p, b.meta_bytes, hipMemcpyHostToDevice, c.stream));
+    if (timed) PMS_HIP(hipEventRecord(c.ev[0], c.stream));
+    PMS_HIP(pms::launch_windows(reinterpret_cast<const pms_win_job*>(dm + b.off_jobs),
+                                static_cast<int32_t>(b.jobs.size()), b.max_t,
+                                c.d_raw.as<uint8_t>(), c.d_win.as<uint32_t>(),
+                                reinterpret_cast<uint32_t*>(dm + b.off_bad), c.stream));
+    if (timed) PMS_HIP(hipEventRecord(c.ev[1], c.stream));
+    PMS_HIP(pms::launch_search(reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
+                               reinterpret_cast<const pms_work_item*>(dm + b.off_work),
+                               static_cast<uint32_t>(b.work.size()),
+                               reinterpret_cast<pms_dev_state*>(dm + b.off_state),
+                               reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves,
+                               c.stream));
+    if (timed) PMS_HIP(hipEventRecord(c.ev[2], c.stream));
+    PMS_HIP(hipMemcpyAsync(c.h_back.as<char>(b.off_state), dm + b.off_state,
+                           b.meta_bytes - b.off_state, hipMemcpyDeviceToHost, c.stream));
+    return PMS_OK;
+}
+
+std::string graph_signature(const Ctx& c, const Batch& b, const pms_config& cfg) {
+    std::ostringstream o;
+    o << c.d_raw.p << ':' << c.d_win.p << ':' << c.d_out.p << ':' << c.d_meta.p << ':'
+      << c.h_raw.p << ':' << c.h_meta.p << ':' << c.h_back.p << ':' << b.raw_bytes << ':'
+      << b.meta_bytes << ':' << b.off_state << ':' << b.jobs.size() << ':' << b.work.size()
+      << ':' << b.max_n << ':' << b.max_t << ':' << cfg.chunk << ':' << cfg.wg_waves << ':'
+      << cfg.wgs_per_cu << ':' << b.shape.size() << ':' << b.off_insts << ':' << b.off_jobs << ':'
+      << b.off_work << ':' << b.off_ctr << ':' << b.off_bad;
+    return o.str();
+}
+
+// Runs a staged batch: eagerly (timed with events) or through the graph.
+int run_batch(Ctx& c, Batch& b, const pms_config& cfg, bool use_graph) {
+    uint32_t grid = 0, waves = 0, qw = 0;
+    PMS_TRY(launch_shape(c, cfg, b.max_n, &grid, &waves, &qw));
+    if (use_graph) {
+        const std::string sig = graph_signature(c, b, cfg);
+        if (!c.gexec || sig != c.gsig) {
+            if (c.gexec) {
+                (void)hipGraphExecDestroy(c.gexec);
+                c.gexec = nullptr;
+            }
+            PMS_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+            const int s = enqueue_batch(c, b, false, grid, waves, qw);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(c.stream, &graph);
+            if (s != PMS_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return s;
+            }
+            PMS_HIP(e);
+            const hipError_t ei = hipGraphInstantiate(&c.gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            PMS_HIP(ei);
+            c.gsig = sig;
+        }
+        PMS_HIP(hipEventRecord(c.ev[0], c.stream));
+        PMS_HIP(hipGraphLaunch(c.gexec, c.stream));
+        PMS_HIP(hipEventRecord(c.ev[2], c.stream));
+        PMS_HIP(hipStreamSynchronize(c.stream));
+        float ms = 0;
+        PMS_HIP(hipEventElapsedTime(&ms, c.ev[0], c.ev[2]));
+        c.last.kernel_ms = ms;  // whole graph: copies + both kernels
+        c.last.windows_ms = 0;
+    } else {
+        PMS_TRY(enqueue_batch(c, b, true, grid, waves, qw));
+        PMS_HIP(hipStreamSynchronize(c.stream));
+        float w_ms = 0, k_ms = 0;
+        PMS_HIP(hipEventElapsedTime(&w_ms, c.ev[0], c.ev[1]));
+        PMS_HIP(hipEventElapsedTime(&k_ms, c.ev[1], c.ev[2]));
+        c.last.windows_ms = w_ms;
+        c.last.kernel_ms = k_ms;
+    }
+    c.last.grid = grid;
+    c.last.wg_waves = waves;
+    c.last.chunk = cfg.chunk;
+    c.last_pending = false;
+    return PMS_OK;
+}
+
+bool use_graph_default() {
+    const char* v = getenv("PMS_NO_GRAPH");
+    return !(v && *v && *v != '0');
+}
+
+// Host-level solve of a set of already validated instances.  caps[i] is the
+// caller's capacity; outs[i] its buffer.  Fills counts and per-instance status.
+int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
+                    const std::vector<const char* const*>& rows,
+                    const std::vector<uint32_t*>& outs, const std::vector<uint64_t>& caps,
+                    std::vector<int>& status, std::vector<uint64_t>& counts,
+                    std::vector<double>& latency, bool use_graph) {
+    const size_t m = shapes.size();
+    const pms_config cfg = c.cfg;
+    Batch b;
+    b.shape = shapes;
+    b.rows = rows;
+    b.out_cap.assign(m, 0);
+    plan_batch(b, cfg);
+    PMS_TRY(stage_batch(c, b));
+    PMS_TRY(run_batch(c, b, cfg, use_graph));
+    counts.assign(m, 0);
+    latency.assign(m, 0.0);
+    status.assign(m, PMS_OK);
+    const pms_dev_state* st = c.h_back.as<pms_dev_state>(b.off_state);
+    const pms_dev_counters* ctr = c.h_back.as<pms_dev_counters>(b.off_ctr);
+    const uint32_t* bad = c.h_back.as<uint32_t>(b.off_bad);
+    uint64_t visits = 0, wcmp = 0;
+    std::vector<size_t> rerun;
+    for (size_t i = 0; i < m; ++i) {
+        counts[i] = st[i].count;
+        visits += st[i].visits;
+        wcmp += st[i].visits * static_cast<uint64_t>(shapes[i].t - shapes[i].l + 1);
+        latency[i] = st[i].t_done > ctr->t_start ? (st[i].t_done - ctr->t_start) * 1e-5 : 0.0;
+        if (bad[i]) status[i] = fail(PMS_ERR_INVALID, "a byte is not A/C/G/T");
+        if (st[i].items_left != 0 || ctr->error)
+            return fail(PMS_ERR_DEVICE, "search ended with unfinished work items");
+        if (counts[i] > b.out_cap[i]) rerun.push_back(i);
+    }
+    c.last.seq_visits = visits;
+    c.last.window_compares = wcmp;
+    c.last.batches = ctr->batches;
+    c.last.reruns = 0;
+    // Outputs larger than the device estimate: solve those again with the
+    // exact capacity (the count is exact, so one rerun suffices).
+    std::vector<std::vector<uint32_t>> host_out(m);
+    for (size_t i = 0; i < m; ++i) {
+        if (status[i] != PMS_OK || counts[i] > b.out_cap[i]) continue;
+        host_out[i].resize(counts[i]);
+        if (counts[i])
+            PMS_HIP(hipMemcpy(host_out[i].data(), c.d_out.as<uint32_t>() + b.out_off[i],
+                              counts[i] * 4, hipMemcpyDeviceToHost));
+    }
+    for (size_t i : rerun) {
+        Batch r;
+        r.shape = {shapes[i]};
+        r.rows = {rows[i]};
+        r.out_cap = {counts[i]};
+        plan_batch(r, cfg);
+        PMS_TRY(stage_batch(c, r));
+        PMS_TRY(run_batch(c, r, cfg, false));
+        const pms_dev_state* rs = c.h_back.as<pms_dev_state>(r.off_state);
+        if (rs[0].count != counts[i]) return fail(PMS_ERR_DEVICE, "rerun changed the motif count");
+        host_out[i].resize(counts[i]);
+        PMS_HIP(hipMemcpy(host_out[i].data(), c.d_out.as<uint32_t>(), counts[i] * 4,
+                          hipMemcpyDeviceToHost));
+        c.last.reruns++;
+    }
+    // Step a7: ascending order, then the caller's capacity.
+    for (size_t i = 0; i < m; ++i) {
+        if (status[i] != PMS_OK) continue;
+        std::vector<uint32_t>& v = host_out[i];
+        std::sort(v.begin(), v.end());
+        if (std::adjacent_find(v.begin(), v.end()) != v.end())
+            return fail(PMS_ERR_DEVICE, "duplicate motif in device output");
+        const uint64_t k = std::min<uint64_t>(caps[i], v.size());
+        if (k) memcpy(outs[i], v.data(), k * 4);
+        if (v.size() > caps[i])
+            status[i] = fail(PMS_ERR_OVERFLOW, "more motifs than capacity");
+    }
+    return PMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotune helpers: a small FM-shaped instance from a fixed seed.
+// ---------------------------------------------------------------------------
+uint64_t splitmix(uint64_t& s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+std::vector<std::string> synthetic_rows(int32_t n, int32_t t, int32_t l, int32_t d, uint64_t seed) {
+    const char* acgt = "ACGT";
+    std::vector<std::string> rows(n, std::string(t, 'A'));
+    std::string cons(l, 'A');
+    for (auto& ch : cons) ch = acgt[splitmix(seed) & 3];
+    for (auto& r : rows)
+        for (auto& ch : r) ch = acgt[splitmix(seed) & 3];
+    for (auto& r : rows) {
+        std::string inst = cons;
+        std::vector<int> pos(l);
+        std::iota(pos.begin(), pos.end(), 0);
+        for (int k = 0; k < d; ++k) {
+            const int j = k + static_cast<int>(splitmix(seed) % (l - k));
+            std::swap(pos[k], pos[j]);
+            const int b = static_cast<int>(strchr(acgt, inst[pos[k]]) - acgt);
+            inst[pos[k]] = acgt[(b + 1 + splitmix(seed) % 3) & 3];
+        }
+        const int off = static_cast<int>(splitmix(seed) % (t - l + 1));
+        r.replace(off, l, inst);
+    }
+    return rows;
+}
+
+std::string tune_key(const Ctx& c, int32_t n, int32_t t, int32_t l, int32_t d) {
+    std::ostringstream o;
+    o << c.arch << "/cu" << c.cus << "/l" << l << "/d" << d << "/n" << n << "/nw"
+      << align_up(static_cast<size_t>(t - l + 1), 128);
+    return o.str();
+}
+
+// The cache file is one flat JSON object: {"key": [chunk, wg_waves, wgs_per_cu, tail], ...}
+bool cache_lookup(const std::string& path, const std::string& key, pms_config* out) {
+    std::ifstream f(path);
+    if (!f) return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    const std::string pat = "\"" + key + "\": [";
+    const size_t p = s.find(pat);
+    if (p == std::string::npos) return false;
+    unsigned a = 0, b = 0, cc = 0, dd = 0;
+    if (sscanf(s.c_str() + p + pat.size(), "%u, %u, %u, %u", &a, &b, &cc, &dd) != 4) return false;
+    pms_config r{a, b, cc, dd};
+    if (!config_ok(r)) return false;
+    *out = r;
+    return true;
+}
+
+void cache_store(const std::string& path, const std::string& key, const pms_config& cfg) {
+    std::vector<std::pair<std::string, std::string>> entries;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            const size_t a = line.find('"');
+            const size_t b = line.find("\": [");
+            if (a == std::string::npos || b == std::string::npos || b <= a) continue;
+            const std::string k = line.substr(a + 1, b - a - 1);
+            const size_t e = line.find(']', b);
+            if (e == std::string::npos) continue;
+            if (k != key) entries.emplace_back(k, line.substr(b + 4, e - b - 4));
+        }
+    }
+    std::ostringstream v;
+    v << cfg.chunk << ", " << cfg.wg_waves << ", " << cfg.wgs_per_cu << ", " << cfg.tail_split;
+    entries.emplace_back(key, v.str());
+    std::ofstream f(path + ".tmp");
+    f << "{\n";
+    for (size_t i = 0; i < entries.size(); ++i)
+        f << "  \"" << entries[i].first << "\": [" << entries[i].second << "]"
+          << (i + 1 < entries.size() ? ",\n" : "\n");
+    f << "}\n";
+    f.close();
+    rename((path + ".tmp").c_str(), path.c_str());
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* pms_status_string(int status) {
+    switch (status) {
+        case PMS_OK: return "ok";
+        case PMS_ERR_INVALID: return "invalid argument";
+        case PMS_ERR_OVERFLOW: return "output capacity exceeded";
+        case PMS_ERR_NOMEM: return "out of memory";
+        case PMS_ERR_DEVICE: return "device error";
+        default: return "unknown status";
+    }
+}
+
+const char* pms_last_error(void) { return g_last_error.c_str(); }
+
+void pms_decode(uint32_t code, int32_t l, char* out) {
+    if (!out || l < 1 || l > PMS_MAX_L) return;
+    for (int32_t p = 0; p < l; ++p) out[p] = "ACGT"[(code >> (2 * (l - 1 - p))) & 3u];
+}
+
+int32_t pms_window_stride(int32_t t, int32_t l) {
+    if (l < 1 || l > PMS_MAX_L || t < l || t > PMS_MAX_T) return 0;
+    return window_stride(t, l);
+}
+
+int pms_set_config(const pms_config* cfg) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    if (!cfg) {
+        g_ctx.cfg = default_config();
+        return PMS_OK;
+    }
+    const pms_config r = resolve(cfg, g_ctx.cfg);
+    if (!config_ok(r)) return fail(PMS_ERR_INVALID, "configuration field out of range");
+    g_ctx.cfg = r;
+    return PMS_OK;
+}
+
+int pms_get_config(pms_config* cfg) {
+    if (!cfg) return fail(PMS_ERR_INVALID, "cfg is NULL");
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    *cfg = g_ctx.cfg;
+    return PMS_OK;
+}
+
+int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t d,
+              uint32_t* out_motifs, uint64_t* out_count) {
+    g_last_error.clear();
+    if (!out_count) return fail(PMS_ERR_INVALID, "out_count is NULL");
+    const uint64_t cap = *out_count;
+    *out_count = 0;
+    PMS_TRY(validate_shape(n, t, l, d));
+    if (cap > 0 && !out_motifs) return fail(PMS_ERR_INVALID, "out_motifs is NULL with capacity > 0");
+    PMS_TRY(validate_rows(seqs, n, t));
+    PMS_TRY(test_hook());
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    PMS_TRY(init_ctx(g_ctx));
+    std::vector<int> status;
+    std::vector<uint64_t> counts;
+    std::vector<double> lat;
+    PMS_TRY(solve_instances(g_ctx, {Shape{n, t, l, d}}, {seqs}, {out_motifs}, {cap}, status,
+                            counts, lat, false));
+    *out_count = counts[0];
+    return status[0];
+}
+
+int pms_solve_many(const pms_instance* inst, int32_t count, pms_result* results) {
+    g_last_error.clear();
+    if (!inst || !results || count < 0) return fail(PMS_ERR_INVALID, "NULL batch or negative count");
+    std::vector<Shape> shapes;
+    std::vector<const char* const*> rows;
+    std::vector<uint32_t*> outs;
+    std::vector<uint64_t> caps;
+    std::vector<int32_t> index;
+    int first_bad = PMS_OK;
+    std::string first_msg;
+    for (int32_t i = 0; i < count; ++i) {
+        results[i].status = PMS_OK;
+        results[i].reserved = 0;
+        results[i].count = 0;
+        results[i].latency_ms = 0;
+        const pms_instance& q = inst[i];
+        int s = validate_shape(q.n, q.t, q.l, q.d);
+        if (s == PMS_OK && q.capacity > 0 && !q.out_motifs)
+            s = fail(PMS_ERR_INVALID, "out_motifs is NULL with capacity > 0");
+        if (s == PMS_OK) s = validate_rows(q.seqs, q.n, q.t);
+        if (s != PMS_OK) {
+            results[i].status = s;
+            if (first_bad == PMS_OK) {
+                first_bad = s;
+                first_msg = g_last_error;
+            }
+            continue;
+        }
+        shapes.push_back({q.n, q.t, q.l, q.d});
+        rows.push_back(q.seqs);
+        outs.push_back(q.out_motifs);
+        caps.push_back(q.capacity);
+        index.push_back(i);
+    }
+    if (shapes.empty()) {
+        if (first_bad != PMS_OK) g_last_error = first_msg;
+        return first_bad;
+    }
+    PMS_TRY(test_hook());
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    PMS_TRY(init_ctx(g_ctx));
+    std::vector<int> status;
+    std::vector<uint64_t> counts;
+    std::vector<double> lat;
+    PMS_TRY(solve_instances(g_ctx, shapes, rows, outs, caps, status, counts, lat,
+                            use_graph_default()));
+    for (size_t j = 0; j < index.size(); ++j) {
+        pms_result& r = results[index[j]];
+        r.status = status[j];
+        r.count = counts[j];
+        r.latency_ms = lat[j];
+    }
+    int ret = PMS_OK;
+    for (int32_t i = 0; i < count && ret == PMS_OK; ++i) ret = results[i].status;
+    if (ret != PMS_OK && ret == first_bad && !first_msg.empty()) g_last_error = first_msg;
+    return ret;
+}
+
+int pms_last_stats(pms_stats* out) {
+    if (!out) return fail(PMS_ERR_INVALID, "out is NULL");
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    if (c.last_pending) {
+        // A device-level call: read its events and counters now.
+        float w_ms = 0, k_ms = 0;
+        PMS_HIP(hipEventSynchronize(c.ev[2]));
+        PMS_HIP(hipEventElapsedTime(&w_ms, c.ev[0], c.ev[1]));
+        PMS_HIP(hipEventElapsedTime(&k_ms, c.ev[1], c.ev[2]));
+        c.last.windows_ms = w_ms;
+        c.last.kernel_ms = k_ms;
+        if (c.dv_counters) {
+            pms_dev_state st;
+            pms_dev_counters ctr;
+            PMS_HIP(hipMemcpy(&st, c.dv_meta.as<char>(c.dv_state_off), sizeof(st), hipMemcpyDeviceToHost));
+            PMS_HIP(hipMemcpy(&ctr, c.dv_meta.as<char>(c.dv_ctr_off), sizeof(ctr), hipMemcpyDeviceToHost));
+            c.last.seq_visits = st.visits;
+            c.last.window_compares = st.visits * static_cast<uint64_t>(c.dv_nw);
+            c.last.batches = ctr.batches;
+        }
+        c.last_pending = false;
+    }
+    *out = c.last;
+    return PMS_OK;
+}
+
+int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l,
+                      uint32_t* dev_windows, uint32_t* dev_bad, void* stream) {
+    g_last_error.clear();
+    if (!dev_seqs || !dev_windows) return fail(PMS_ERR_INVALID, "NULL device pointer");
+    if (n < 1 || n > PMS_MAX_N || l < 1 || l > PMS_MAX_L || t < l || t > PMS_MAX_T)
+        return fail(PMS_ERR_INVALID, "size out of range");
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    PMS_TRY(init_ctx(c));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // Job table through the device workspace; wait for the previous upload
+    // from the pinned mirror before overwriting it.
+    if (c.dv_copy_live) PMS_HIP(hipEventSynchronize(c.dv_copied));
+    const size_t bytes = align_up(static_cast<size_t>(n) * sizeof(pms_win_job), 256);
+    PMS_TRY(c.hv_meta.ensure(bytes));
+    PMS_TRY(c.dv_meta.ensure(bytes));
+    pms_win_job* jobs = c.hv_meta.as<pms_win_job>();
+    const int32_t stride = window_stride(t, l);
+    for (int32_t r = 0; r < n; ++r)
+        jobs[r] = {static_cast<uint64_t>(r) * t, static_cast<uint64_t>(r) * stride, t, l, stride, 0};
+    PMS_HIP(hipMemcpyAsync(c.dv_meta.p, c.hv_meta.p, bytes, hipMemcpyHostToDevice, s));
+    PMS_HIP(hipEventRecord(c.dv_copied, s));
+    c.dv_copy_live = true;
+    PMS_HIP(pms::launch_windows(c.dv_meta.as<pms_win_job>(), n, t, dev_seqs, dev_windows, dev_bad, s));
+    return PMS_OK;
+}
+
+int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32_t max_n,
+                    const pms_work_item* dev_work, int32_t n_work, pms_dev_state* dev_state,
+                    pms_dev_counters* dev_counters, const pms_config* cfg, void* stream) {
+    g_last_error.clear();
+    if (!dev_instances || !dev_state || !dev_counters || (n_work > 0 && !dev_work))
+        return fail(PMS_ERR_INVALID, "NULL device pointer");
+    if (n_inst < 1 || n_work < 0 || max_n < 1 || max_n > PMS_MAX_N)
+        return fail(PMS_ERR_INVALID, "table size out of range");
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    PMS_TRY(init_ctx(c));
+    const pms_config r = resolve(cfg, c.cfg);
+    if (!config_ok(r)) return fail(PMS_ERR_INVALID, "configuration field out of range");
+    uint32_t grid = 0, waves = 0, qw = 0;
+    PMS_TRY(launch_shape(c, r, max_n, &grid, &waves, &qw));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PMS_HIP(hipEventRecord(c.ev[0], s));
+    PMS_HIP(hipEventRecord(c.ev[1], s));
+    PMS_HIP(pms::launch_search(dev_instances, dev_work, static_cast<uint32_t>(n_work), dev_state,
+                               dev_counters, qw, grid, waves, s));
+    PMS_HIP(hipEventRecord(c.ev[2], s));
+    c.last = pms_stats{};
+    c.last.grid = grid;
+    c.last.wg_waves = waves;
+    c.last.chunk = r.chunk;
+    c.last_pending = true;
+    c.dv_counters = false;
+    return PMS_OK;
+}
+
+int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
+                  uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count, void* stream) {
+    g_last_error.clear();
+    if (!dev_seqs || !dev_count || (capacity > 0 && !dev_out))
+        return fail(PMS_ERR_INVALID, "NULL device pointer");
+    PMS_TRY(validate_shape(n, t, l, d));
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    PMS_TRY(init_ctx(c));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const pms_config cfg = c.cfg;
+    Batch b;
+    b.shape = {Shape{n, t, l, d}};
+    b.out_cap = {capacity > 0 ? capacity : 1};
+    plan_batch(b, cfg);
+    uint32_t grid = 0, waves = 0, qw = 0;
+    PMS_TRY(launch_shape(c, cfg, b.max_n, &grid, &waves, &qw));
+    if (c.dv_copy_live) PMS_HIP(hipEventSynchronize(c.dv_copied));
+    PMS_TRY(c.dv_win.ensure(std::max<size_t>(b.win_words * 4, 256)));
+    PMS_TRY(c.dv_meta.ensure(b.meta_bytes));
+    PMS_TRY(c.hv_meta.ensure(b.meta_bytes));
+    char* hm = c.hv_meta.as<char>();
+    char* dm = c.dv_meta.as<char>();
+    memset(hm, 0, b.meta_bytes);
+    pms_dev_instance* in = reinterpret_cast<pms_dev_instance*>(hm + b.off_insts);
+    in->windows = c.dv_win.as<uint32_t>();
+    in->out = dev_out;
+    in->out_cap = capacity;
+    in->n = n;
+    in->nw_stride = window_stride(t, l);
+    in->l = l;
+    in->d = d;
+    reinterpret_cast<pms_dev_state*>(hm + b.off_state)->items_left = b.items_per_inst[0];
+    memcpy(hm + b.off_jobs, b.jobs.data(), b.jobs.size() * sizeof(pms_win_job));
+    memcpy(hm + b.off_work, b.work.data(), b.work.size() * sizeof(pms_work_item));
+    PMS_HIP(hipMemcpyAsync(dm, hm, b.meta_bytes, hipMemcpyHostToDevice, s));
+    PMS_HIP(hipEventRecord(c.dv_copied, s));
+    c.dv_copy_live = true;
+    PMS_HIP(hipEventRecord(c.ev[0], s));
+    PMS_HIP(pms::launch_windows(reinterpret_cast<const pms_win_job*>(dm + b.off_jobs), n, t,
+                                dev_seqs, c.dv_win.as<uint32_t>(),
+                                reinterpret_cast<uint32_t*>(dm + b.off_bad), s));
+    PMS_HIP(hipEventRecord(c.ev[1], s));
+    PMS_HIP(pms::launch_search(reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
+                               reinterpret_cast<const pms_work_item*>(dm + b.off_work),
+                               static_cast<uint32_t>(b.work.size()),
+                               reinterpret_cast<pms_dev_state*>(dm + b.off_state),
+                               reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves, s));
+    PMS_HIP(hipEventRecord(c.ev[2], s));
+    PMS_HIP(hipMemcpyAsync(dev_count, dm + b.off_state + offsetof(pms_dev_state, count),
+                           sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    c.last = pms_stats{};
+    c.last.grid = grid;
+    c.last.wg_waves = waves;
+    c.last.chunk = cfg.chunk;
+    c.last_pending = true;
+    c.dv_counters = true;
+    c.dv_state_off = b.off_state;
+    c.dv_ctr_off = b.off_ctr;
+    c.dv_nw = t - l + 1;
+    return PMS_OK;
+}
+
+int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_path,
+                 pms_config* best) {
+    g_last_error.clear();
+    PMS_TRY(validate_shape(n, t, l, d));
+    std::string path = cache_path ? cache_path : "";
+    if (path.empty())
+        if (const char* v = getenv("PMS_AUTOTUNE_CACHE")) path = v;
+    std::unique_lock<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    PMS_TRY(init_ctx(c));
+    const std::string key = tune_key(c, n, t, l, d);
+    pms_config found;
+    if (!path.empty() && cache_lookup(path, key, &found)) {
+        c.cfg = found;
+        if (best) *best = found;
+        return PMS_OK;
+    }
+    const std::vector<std::string> rows = synthetic_rows(n, t, l, d, 0x1403131300ull + l * 64 + d);
+    std::vector<const char*> ptrs(n);
+    for (int32_t i = 0; i < n; ++i) ptrs[i] = rows[i].data();
+    const uint64_t total = 1ull << (2 * l);
+    pms_config best_cfg = c.cfg;
+    double best_ms = 1e300;
+    const uint32_t chunks[] = {1u << 11, 1u << 12, 1u << 13, 1u << 14, 1u << 15, 1u << 16};
+    const uint32_t waves[] = {1, 2, 4, 8};
+    for (uint32_t ch : chunks) {
+        if (ch > total && ch != chunks[0]) continue;
+        for (uint32_t w : waves) {
+            pms_config cfg{ch, w, 0, 8};
+            Batch b;
+            b.shape = {Shape{n, t, l, d}};
+            b.rows = {ptrs.data()};
+            b.out_cap = {0};
+            plan_batch(b, cfg);
+            PMS_TRY(stage_batch(c, b));
+            double ms = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                PMS_TRY(run_batch(c, b, cfg, false));
+                ms = std::min(ms, c.last.kernel_ms);
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_cfg = cfg;
+            }
+        }
+    }
+    c.cfg = best_cfg;
+    if (!path.empty()) cache_store(path, key, best_cfg);
+    if (best) *best = best_cfg;
+    return PMS_OK;
+}
+
+}  // extern "C"

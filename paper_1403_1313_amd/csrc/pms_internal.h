@@ -1,0 +1,44 @@
+// pms_internal.h -- shared between the kernels and the host library (not
+// part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pms.h"
+
+// Stage-queue slots per sequence stage per wavefront.  At most one queue is
+// ever at or above 64 entries and it is scanned before anything else is
+// pushed, so every queue stays below 128.
+#define PMS_QCAP 128u
+// Per-wavefront staging slots for final survivors (flushed at > OUTBUF-64).
+#define PMS_OUTBUF 256u
+
+// One row for the window-building kernel.
+typedef struct {
+    uint64_t src_off;  // byte offset of the row in the packed input
+    uint64_t dst_off;  // uint32 offset of the row's windows
+    int32_t t, l, stride, inst;
+} pms_win_job;
+
+namespace pms {
+
+hipError_t launch_windows(const pms_win_job* jobs, int32_t rows, int32_t max_t,
+                          const uint8_t* seqs, uint32_t* windows, uint32_t* bad,
+                          hipStream_t stream);
+
+hipError_t launch_search(const pms_dev_instance* insts, const pms_work_item* work,
+                         uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
+                         uint32_t q_words, uint32_t grid, uint32_t wg_waves, hipStream_t stream);
+
+hipError_t launch_fill(uint32_t* p, uint64_t words, uint32_t v, hipStream_t stream);
+
+const void* search_kernel_symbol();
+
+// LDS words one wavefront of the search kernel needs for instances of up to
+// max_n sequences.
+inline uint32_t queue_words(int32_t max_n) {
+    return static_cast<uint32_t>(max_n > 1 ? max_n - 1 : 0) * PMS_QCAP;
+}
+
+}  // namespace pms

@@ -1,0 +1,382 @@
+// pms_kernels.hip -- gfx950 kernels of the planted (l, d) motif search.
+//
+// Two kernels make up one solve:
+//
+//   pms_windows_kernel  (steps a1 + a2)  One workgroup per sequence row.  The
+//       row's bytes are encoded to 2-bit codes (A=0 C=1 G=2 T=3), packed 16
+//       bases per 32-bit word into LDS, and every window of length l (the t-l+1
+//       substrings of Section III.A) is written out in bit-plane form:
+//       bit 16 + (l-1-p) holds the high bit of base p and bit (l-1-p) its low
+//       bit.  Rows are padded to a multiple of 16 windows with copies of
+//       window 0 (a repeated window cannot change a minimum).
+//
+//   pms_search_kernel   (steps a3 - a6)  Persistent workgroups; every 64-lane
+//       wavefront works on its own.  It claims numbered work items (index
+//       ranges of candidate l-mers, Section IV.A) with one global atomic and
+//       generates the candidates of a range on the fly.  A wavefront always
+//       scans 64 candidates against ONE sequence s at a time, so the window
+//       index and the sequence are wave-uniform and every window arrives through
+//       the scalar data cache as an SGPR operand: one compare is
+//       v_xor (candidate ^ window), v_or_b32_sdwa (merge the two bit planes),
+//       v_bcnt (mismatching positions) and half a v_min3 (running minimum).
+//       Candidates whose minimum over the windows of s exceeds d are dropped
+//       on the spot and never see sequences s+1.. (the enhanced rule of
+//       Section III.A, applied per lane); the others are appended to an LDS
+//       queue for stage s+1 through a wavefront ballot + mbcnt prefix.  A
+//       queue that reaches 64 entries is scanned next, deepest stage first,
+//       so the queues stay below 128 entries and no lane idles on a candidate
+//       that already failed.  Candidates that pass the last sequence are
+//       converted to motif codes and staged in a per-wavefront LDS buffer
+//       that is flushed with a single global atomicAdd per flush.
+//
+// Candidates are numbered in bit-plane order inside the kernel: candidate k
+// has high plane k >> l and low plane k & (2^l - 1).  This enumerates the same
+// set as the dictionary order; survivors are converted to the dictionary code
+// (bit 2q+1 = high-plane bit q, bit 2q = low-plane bit q) when written out.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pms.h"
+#include "pms_internal.h"
+
+namespace {
+
+typedef __attribute__((address_space(4))) const uint32_t cu32;
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Number of set bits of m below the calling lane.
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// (x >> 16) | (x & 0xffff) in one instruction: the OR of the two bit planes
+// of an XOR difference marks every mismatching base position.
+__device__ __forceinline__ uint32_t or_planes(uint32_t x) {
+    uint32_t r;
+    asm("v_or_b32_sdwa %0, %1, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 "
+        "src1_sel:WORD_0"
+        : "=v"(r)
+        : "v"(x));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Inserts a zero bit above every bit of a 16-bit value.
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {
+    x &= 0xffffu;
+    x = (x | (x << 8)) & 0x00ff00ffu;
+    x = (x | (x << 4)) & 0x0f0f0f0fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+// Bit-plane candidate -> motif code (first base in the top digit).
+__device__ __forceinline__ uint32_t plane_to_code(uint32_t c) {
+    return (spread16(c >> 16) << 1) | spread16(c);
+}
+
+// Smallest mismatch count between `cand` and the windows W[0 .. 16*groups).
+// W is wave-uniform, so its words are scalar loads.
+__device__ __forceinline__ uint32_t scan_sequence(cu32* W, uint32_t groups, uint32_t cand) {
+    uint32_t a0 = 0xffu, a1 = 0xffu;
+    for (uint32_t g = 0; g < groups; ++g, W += 16) {
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) {
+            const uint32_t m0 = __builtin_popcount(or_planes(cand ^ W[k + 0]));
+            const uint32_t m1 = __builtin_popcount(or_planes(cand ^ W[k + 1]));
+            const uint32_t m2 = __builtin_popcount(or_planes(cand ^ W[k + 2]));
+            const uint32_t m3 = __builtin_popcount(or_planes(cand ^ W[k + 3]));
+            a0 = min3u(a0, m0, m1);
+            a1 = min3u(a1, m2, m3);
+        }
+    }
+    return a0 < a1 ? a0 : a1;
+}
+
+// Reads a wave-uniform record of read-only data through the scalar cache.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "records are whole words");
+    cu32* w = (cu32*)(p);
+    T r;
+    uint32_t* rw = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) rw[i] = w[i];
+    return r;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// Steps a1 + a2: encode, pack into LDS, write bit-plane windows.
+// --------------------------------------------------------------------------
+extern "C" __global__ void __launch_bounds__(256)
+pms_windows_kernel(const pms_win_job* __restrict__ jobs, const uint8_t* __restrict__ seqs,
+                   uint32_t* __restrict__ windows, uint32_t* __restrict__ bad) {
+    extern __shared__ uint32_t packed[];
+    const pms_win_job job = jobs[blockIdx.x];
+    const uint8_t* row = seqs + job.src_off;
+    const int t = job.t, l = job.l, stride = job.stride;
+    const int words = (t + 15) >> 4;
+
+    // a1: 16 bases per word, base q of the word in bits [2q, 2q+1].
+    bool saw_bad = false;
+    for (int w = threadIdx.x; w < words; w += blockDim.x) {
+        uint32_t v = 0;
+        const int q_end = min(16, t - 16 * w);
+        for (int q = 0; q < q_end; ++q) {
+            const uint32_t c = row[16 * w + q] | 0x20u;  // fold upper case onto lower
+            uint32_t code;
+            if (c == 'a') code = 0;
+            else if (c == 'c') code = 1;
+            else if (c == 'g') code = 2;
+            else if (c == 't') code = 3;
+            else { code = 0; saw_bad = true; }
+            v |= code << (2 * q);
+        }
+        packed[w] = v;
+    }
+    if (threadIdx.x == 0) packed[words] = 0;  // a window may read one word past the row
+    if (saw_bad && bad) bad[job.inst] = 1u;
+    __syncthreads();
+
+    // a2: window j covers bases j .. j+l-1 (l <= 16, so at most two words).
+    const int nw = t - l + 1;
+    uint32_t* dst = windows + job.dst_off;
+    for (int j = threadIdx.x; j < stride; j += blockDim.x) {
+        const int jj = j < nw ? j : 0;
+        const int wq = jj >> 4, sh = 2 * (jj & 15);
+        const uint64_t two = (static_cast<uint64_t>(packed[wq + 1]) << 32) | packed[wq];
+        const uint32_t bits = static_cast<uint32_t>(two >> sh);
+        uint32_t hi = 0, lo = 0;
+        for (int p = 0; p < l; ++p) {
+            const uint32_t b = (bits >> (2 * p)) & 3u;
+            hi |= (b >> 1) << (l - 1 - p);
+            lo |= (b & 1u) << (l - 1 - p);
+        }
+        dst[j] = (hi << 16) | lo;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Steps a3 - a6: persistent candidate sweep.
+// --------------------------------------------------------------------------
+extern "C" __global__ void __launch_bounds__(1024)
+pms_search_kernel(const pms_dev_instance* __restrict__ insts,
+                  const pms_work_item* __restrict__ work, uint32_t n_work,
+                  pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
+                  uint32_t q_words) {
+    extern __shared__ uint32_t lds[];
+    constexpr uint32_t kNone = 0xffffffffu;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uni(threadIdx.x >> 6);
+    uint32_t* const q = lds + wave * (q_words + PMS_OUTBUF);  // stage queues
+    uint32_t* const ob = q + q_words;                         // survivor staging
+
+    uint32_t cur = kNone;     // instance whose candidates the queues hold
+    uint32_t pending = 0;     // claimed items of `cur` not yet retired
+    uint32_t stash = kNone;   // claimed item of another instance, waiting
+    bool more = true;         // the work table may still have items
+    uint64_t next = 0, end = 0;
+    uint64_t visits = 0, batches = 0;
+    uint32_t nob = 0;         // entries in ob
+    uint32_t counts = 0;      // lane s: candidates queued for stage s
+
+    cu32* W = nullptr;
+    uint32_t* out = nullptr;
+    uint64_t cap = 0;
+    uint32_t n = 0, nwp = 0, l = 0, d = 0, lmask = 0;
+
+    for (;;) {
+        uint32_t s, cand = 0;
+        bool active;
+        const uint64_t full = ballot(counts >= 64u);
+        if (full) {
+            // Deepest full queue first: pop its newest 64 entries.
+            s = 63u - static_cast<uint32_t>(__builtin_clzll(full));
+            const uint32_t c = __builtin_amdgcn_readlane(counts, s);
+            cand = q[(s - 1) * PMS_QCAP + c - 64u + lane];
+            active = true;
+            if (lane == s) counts -= 64u;
+        } else if (next < end) {
+            // Stage 0: the next 64 candidate numbers of the claimed range.
+            s = 0;
+            const uint64_t k = next + lane;
+            active = k < end;
+            const uint32_t kk = static_cast<uint32_t>(k);
+            cand = ((kk >> l) << 16) | (kk & lmask);
+            next += 64;
+        } else {
+            if (stash == kNone && more) {
+                uint32_t item = 0;
+                if (lane == 0) item = atomicAdd(&ctr->next_item, 1u);
+                item = uni(item);
+                if (item == 0 && lane == 0) ctr->t_start = wall_clock64();
+                if (item >= n_work) {
+                    more = false;
+                } else {
+                    const pms_work_item wi = load_uniform(work + item);
+                    if (wi.inst == cur) {
+                        ++pending;
+                        next = wi.begin;
+                        end = wi.begin + wi.len;
+                    } else {
+                        stash = item;
+                    }
+                }
+                continue;
+            }
+            const uint64_t nz = ballot(counts > 0u);
+            if (nz == 0) {
+                // Queues empty: every candidate of `cur` this wave claimed is done.
+                if (cur != kNone) {
+                    if (nob) {
+                        uint64_t base = 0;
+                        if (lane == 0)
+                            base = atomicAdd(reinterpret_cast<unsigned long long*>(&state[cur].count),
+                                             static_cast<unsigned long long>(nob));
+                        base = uni64(base);
+                        for (uint32_t i = lane; i < nob; i += 64u)
+                            if (base + i < cap) out[base + i] = ob[i];
+                        nob = 0;
+                    }
+                    if (lane == 0) {
+                        atomicAdd(reinterpret_cast<unsigned long long*>(&state[cur].visits),
+                                  static_cast<unsigned long long>(visits));
+                        const uint32_t old = atomicSub(&state[cur].items_left, pending);
+                        if (old == pending) state[cur].t_done = wall_clock64();
+                    }
+                    visits = 0;
+                    pending = 0;
+                    cur = kNone;
+                }
+                if (stash == kNone) break;
+                const pms_work_item wi = load_uniform(work + stash);
+                const pms_dev_instance in = load_uniform(insts + wi.inst);
+                stash = kNone;
+                if (in.n < 1 || (static_cast<uint32_t>(in.n) - 1u) * PMS_QCAP > q_words) {
+                    // More stages than the launch's LDS queues hold: refuse the item.
+                    if (lane == 0) atomicOr(&ctr->error, 1u);
+                    continue;
+                }
+                cur = wi.inst;
+                W = (cu32*)(in.windows);
+                out = in.out;
+                cap = in.out_cap;
+                n = static_cast<uint32_t>(in.n);
+                nwp = static_cast<uint32_t>(in.nw_stride);
+                l = static_cast<uint32_t>(in.l);
+                d = static_cast<uint32_t>(in.d);
+                lmask = (1u << l) - 1u;
+                pending = 1;
+                next = wi.begin;
+                end = wi.begin + wi.len;
+                continue;
+            }
+            // Drain: the shallowest non-empty queue (fewer than 64 entries).
+            s = static_cast<uint32_t>(__builtin_ctzll(nz));
+            const uint32_t c = __builtin_amdgcn_readlane(counts, s);
+            active = lane < c;
+            if (active) cand = q[(s - 1) * PMS_QCAP + lane];
+            if (lane == s) counts = 0;
+        }
+
+        // One sequence scan for the 64 lanes.
+        const uint32_t best = scan_sequence(W + s * nwp, nwp >> 4, cand);
+        const bool pass = active && best <= d;
+        visits += __builtin_popcountll(ballot(active));
+        ++batches;
+        const uint64_t pm = ballot(pass);
+        if (pm) {
+            const uint32_t r = rank_below(pm);
+            const uint32_t np = static_cast<uint32_t>(__builtin_popcountll(pm));
+            if (s + 1 < n) {
+                const uint32_t base = __builtin_amdgcn_readlane(counts, s + 1);
+                if (pass) q[s * PMS_QCAP + base + r] = cand;
+                if (lane == s + 1) counts += np;
+            } else {
+                if (pass) ob[nob + r] = plane_to_code(cand);
+                nob += np;
+                if (nob > PMS_OUTBUF - 64u) {
+                    uint64_t base = 0;
+                    if (lane == 0)
+                        base = atomicAdd(reinterpret_cast<unsigned long long*>(&state[cur].count),
+                                         static_cast<unsigned long long>(nob));
+                    base = uni64(base);
+                    for (uint32_t i = lane; i < nob; i += 64u)
+                        if (base + i < cap) out[base + i] = ob[i];
+                    nob = 0;
+                }
+            }
+        }
+    }
+    if (lane == 0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->batches),
+                  static_cast<unsigned long long>(batches));
+}
+
+// --------------------------------------------------------------------------
+// Small helpers used by the host library.
+// --------------------------------------------------------------------------
+
+// Clears `words` 32-bit words (used instead of a memset so that the same
+// sequence can be captured into a graph).
+extern "C" __global__ void pms_fill_kernel(uint32_t* __restrict__ p, uint64_t words, uint32_t v) {
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < words;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+namespace pms {
+
+hipError_t launch_windows(const pms_win_job* jobs, int32_t rows, int32_t max_t,
+                          const uint8_t* seqs, uint32_t* windows, uint32_t* bad,
+                          hipStream_t stream) {
+    if (rows <= 0) return hipSuccess;
+    const size_t lds = (static_cast<size_t>((max_t + 15) / 16) + 1) * sizeof(uint32_t);
+    hipLaunchKernelGGL(pms_windows_kernel, dim3(rows), dim3(256), lds, stream, jobs, seqs,
+                       windows, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_search(const pms_dev_instance* insts, const pms_work_item* work,
+                         uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
+                         uint32_t q_words, uint32_t grid, uint32_t wg_waves, hipStream_t stream) {
+    const size_t lds = static_cast<size_t>(wg_waves) * (q_words + PMS_OUTBUF) * sizeof(uint32_t);
+    hipLaunchKernelGGL(pms_search_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream, insts,
+                       work, n_work, state, ctr, q_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(uint32_t* p, uint64_t words, uint32_t v, hipStream_t stream) {
+    if (words == 0) return hipSuccess;
+    const uint64_t blocks64 = (words + 255) / 256;
+    const uint32_t blocks = static_cast<uint32_t>(blocks64 < 1024 ? blocks64 : 1024);
+    hipLaunchKernelGGL(pms_fill_kernel, dim3(blocks), dim3(256), 0, stream, p, words, v);
+    return hipGetLastError();
+}
+
+const void* search_kernel_symbol() { return reinterpret_cast<const void*>(&pms_search_kernel); }
+
+}  // namespace pms

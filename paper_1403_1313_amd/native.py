@@ -1,0 +1,259 @@
+"""ctypes binding of libpms.so (include/pms.h).  Argument marshalling only.
+
+Every computation runs in the library's GPU kernels.  If libpms.so has not
+been built this module raises ImportError; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpms.so")
+
+PMS_OK, PMS_ERR_INVALID, PMS_ERR_OVERFLOW, PMS_ERR_NOMEM, PMS_ERR_DEVICE = range(5)
+PMS_MAX_L, PMS_MAX_N, PMS_MAX_T = 16, 64, 1 << 17
+
+SYMBOLS = ["pms_solve", "pms_solve_many", "pms_decode", "pms_status_string", "pms_last_error",
+           "pms_set_config", "pms_get_config", "pms_autotune", "pms_last_stats",
+           "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev"]
+
+
+class PmsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)} ({status}): {message}")
+        self.status = status
+        self.message = message
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("seqs", ctypes.POINTER(ctypes.c_char_p)), ("n", ctypes.c_int32),
+                ("t", ctypes.c_int32), ("l", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("out_motifs", ctypes.POINTER(ctypes.c_uint32)), ("capacity", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("count", ctypes.c_uint64), ("latency_ms", ctypes.c_double)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_uint32), ("wg_waves", ctypes.c_uint32),
+                ("wgs_per_cu", ctypes.c_uint32), ("tail_split", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double), ("windows_ms", ctypes.c_double),
+                ("seq_visits", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("window_compares", ctypes.c_uint64), ("grid", ctypes.c_uint32),
+                ("wg_waves", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("reruns", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
+
+
+class DevInstance(ctypes.Structure):
+    _fields_ = [("windows", ctypes.c_uint64), ("out", ctypes.c_uint64), ("out_cap", ctypes.c_uint64),
+                ("n", ctypes.c_int32), ("nw_stride", ctypes.c_int32), ("l", ctypes.c_int32),
+                ("d", ctypes.c_int32)]
+
+
+class WorkItem(ctypes.Structure):
+    _fields_ = [("begin", ctypes.c_uint64), ("len", ctypes.c_uint32), ("inst", ctypes.c_uint32)]
+
+
+class DevState(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("visits", ctypes.c_uint64), ("t_done", ctypes.c_uint64),
+                ("items_left", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class DevCounters(ctypes.Structure):
+    _fields_ = [("next_item", ctypes.c_uint32), ("error", ctypes.c_uint32),
+                ("batches", ctypes.c_uint64), ("t_start", ctypes.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'` "
+                          "or `python paper_1403_1313_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    u32p, u64p, vp = P(ctypes.c_uint32), P(ctypes.c_uint64), ctypes.c_void_p
+    i32 = ctypes.c_int32
+    sig = {
+        "pms_solve": ([P(ctypes.c_char_p), i32, i32, i32, i32, u32p, u64p], ctypes.c_int),
+        "pms_solve_many": ([P(Instance), i32, P(Result)], ctypes.c_int),
+        "pms_decode": ([ctypes.c_uint32, i32, ctypes.c_char_p], None),
+        "pms_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "pms_last_error": ([], ctypes.c_char_p),
+        "pms_set_config": ([P(Config)], ctypes.c_int),
+        "pms_get_config": ([P(Config)], ctypes.c_int),
+        "pms_autotune": ([i32, i32, i32, i32, ctypes.c_char_p, P(Config)], ctypes.c_int),
+        "pms_last_stats": ([P(Stats)], ctypes.c_int),
+        "pms_window_stride": ([i32, i32], i32),
+        "pms_build_windows": ([vp, i32, i32, i32, vp, vp, vp], ctypes.c_int),
+        "pms_step_launch": ([vp, i32, i32, vp, i32, vp, vp, P(Config), vp], ctypes.c_int),
+        "pms_solve_dev": ([vp, i32, i32, i32, i32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return _lib.pms_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return _lib.pms_last_error().decode()
+
+
+def _check(status: int, allow=(PMS_OK,)):
+    if status not in allow:
+        raise PmsError(status, last_error())
+    return status
+
+
+def _rows(seqs) -> Tuple[ctypes.Array, list, int, int]:
+    """char* array for n rows (list of str/bytes or an (n, t) uint8 array)."""
+    if isinstance(seqs, np.ndarray):
+        m = np.ascontiguousarray(seqs, dtype=np.uint8)
+        rows = [m[i].tobytes() for i in range(m.shape[0])]
+    else:
+        rows = [s.encode() if isinstance(s, str) else bytes(s) for s in seqs]
+    n = len(rows)
+    t = len(rows[0]) if rows else 0
+    arr = (ctypes.c_char_p * max(n, 1))(*rows) if n else (ctypes.c_char_p * 1)()
+    return arr, rows, n, t
+
+
+def solve_raw(seqs, l: int, d: int, capacity: Optional[int] = None, t: Optional[int] = None):
+    """pms_solve: (status, count, motifs[:min(count, capacity)])."""
+    arr, keep, n, t0 = _rows(seqs)
+    t = t0 if t is None else t
+    if capacity is None:
+        capacity = 1 << 20
+    out = np.zeros(max(capacity, 1), dtype=np.uint32)
+    cnt = ctypes.c_uint64(capacity)
+    st = _lib.pms_solve(arr, n, t, l, d, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+                        if capacity > 0 else None, ctypes.byref(cnt))
+    del keep
+    k = min(int(cnt.value), capacity)
+    return st, int(cnt.value), out[:k].copy()
+
+
+def solve(seqs, l: int, d: int) -> np.ndarray:
+    """Sorted uint32 motif codes of one instance (regrows on overflow)."""
+    st, cnt, res = solve_raw(seqs, l, d, capacity=1 << 16)
+    if st == PMS_ERR_OVERFLOW:
+        st, cnt, res = solve_raw(seqs, l, d, capacity=cnt)
+    _check(st)
+    return res
+
+
+def solve_many(instances: Sequence[Tuple[object, int, int]], capacities=None):
+    """pms_solve_many over [(seqs, l, d), ...]: (status, [motifs], [Result])."""
+    m = len(instances)
+    insts = (Instance * max(m, 1))()
+    keep, outs = [], []
+    for i, (seqs, l, d) in enumerate(instances):
+        arr, rows, n, t = _rows(seqs)
+        cap = (1 << 16) if capacities is None else int(capacities[i])
+        out = np.zeros(max(cap, 1), dtype=np.uint32)
+        keep.append((arr, rows))
+        outs.append(out)
+        insts[i].seqs = ctypes.cast(arr, ctypes.POINTER(ctypes.c_char_p))
+        insts[i].n, insts[i].t, insts[i].l, insts[i].d = n, t, l, d
+        insts[i].out_motifs = out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if cap else None
+        insts[i].capacity = cap
+    res = (Result * max(m, 1))()
+    st = _lib.pms_solve_many(insts, m, res)
+    results = [res[i] for i in range(m)]
+    motifs = [outs[i][:min(int(results[i].count), len(outs[i]))].copy() for i in range(m)]
+    return st, motifs, results
+
+
+def decode(code: int, l: int) -> str:
+    buf = ctypes.create_string_buffer(l)
+    _lib.pms_decode(int(code), int(l), buf)
+    return buf.raw[:l].decode()
+
+
+def set_config(chunk=0, wg_waves=0, wgs_per_cu=0, tail_split=8, reset=False):
+    if reset:
+        return _check(_lib.pms_set_config(None))
+    cfg = Config(chunk, wg_waves, wgs_per_cu, tail_split)
+    return _check(_lib.pms_set_config(ctypes.byref(cfg)))
+
+
+def get_config() -> dict:
+    cfg = Config()
+    _check(_lib.pms_get_config(ctypes.byref(cfg)))
+    return cfg.as_dict()
+
+
+def autotune(n: int, t: int, l: int, d: int, cache_path: Optional[str] = None) -> dict:
+    cfg = Config()
+    _check(_lib.pms_autotune(n, t, l, d, cache_path.encode() if cache_path else None,
+                             ctypes.byref(cfg)))
+    return cfg.as_dict()
+
+
+def last_stats() -> dict:
+    s = Stats()
+    _check(_lib.pms_last_stats(ctypes.byref(s)))
+    return s.as_dict()
+
+
+def window_stride(t: int, l: int) -> int:
+    return int(_lib.pms_window_stride(t, l))
+
+
+# ---------------------------------------------------------------------------
+# Device level (torch tensors supply device memory and the stream).
+# ---------------------------------------------------------------------------
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def build_windows(dev_seqs, n: int, t: int, l: int, dev_windows, dev_bad=None, stream=None):
+    return _check(_lib.pms_build_windows(
+        dev_seqs.data_ptr(), n, t, l, dev_windows.data_ptr(),
+        dev_bad.data_ptr() if dev_bad is not None else None, _stream_handle(stream)))
+
+
+def solve_dev(dev_seqs, n: int, t: int, l: int, d: int, dev_out, capacity: int, dev_count,
+              stream=None):
+    return _check(_lib.pms_solve_dev(
+        dev_seqs.data_ptr(), n, t, l, d, dev_out.data_ptr() if capacity else None, capacity,
+        dev_count.data_ptr(), _stream_handle(stream)))
+
+
+def step_launch(dev_instances, n_inst: int, max_n: int, dev_work, n_work: int, dev_state,
+                dev_counters, config: Optional[dict] = None, stream=None):
+    cfg = Config(**config) if config else None
+    return _check(_lib.pms_step_launch(
+        dev_instances.data_ptr(), n_inst, max_n, dev_work.data_ptr() if n_work else None, n_work,
+        dev_state.data_ptr(), dev_counters.data_ptr(),
+        ctypes.byref(cfg) if cfg is not None else None, _stream_handle(stream)))

@@ -1,0 +1,167 @@
+"""The C-ABI library: exported symbols, struct layouts and every host-side
+error path (all of them run before any device call, so no GPU is needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pms.h")
+
+nat = pytest.importorskip("paper_1403_1313_amd.native",
+                          reason="libpms.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pms_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) == 13
+    assert sorted(nat.SYMBOLS) == names
+    lib = ctypes.CDLL(nat.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof/offsetof from the C header compiled by gcc == the ctypes mirrors."""
+    prog = tmp_path / "layout.c"
+    fields = {
+        "pms_instance": ["seqs", "n", "t", "l", "d", "out_motifs", "capacity"],
+        "pms_result": ["status", "count", "latency_ms"],
+        "pms_config": ["chunk", "wg_waves", "wgs_per_cu", "tail_split"],
+        "pms_stats": ["kernel_ms", "windows_ms", "seq_visits", "batches", "window_compares",
+                      "grid", "wg_waves", "chunk", "reruns"],
+        "pms_dev_instance": ["windows", "out", "out_cap", "n", "nw_stride", "l", "d"],
+        "pms_work_item": ["begin", "len", "inst"],
+        "pms_dev_state": ["count", "visits", "t_done", "items_left"],
+        "pms_dev_counters": ["next_item", "error", "batches", "t_start"],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pms.h"', "int main(void){"]
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0;}")
+    prog.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    mirrors = {"pms_instance": nat.Instance, "pms_result": nat.Result, "pms_config": nat.Config,
+               "pms_stats": nat.Stats, "pms_dev_instance": nat.DevInstance,
+               "pms_work_item": nat.WorkItem, "pms_dev_state": nat.DevState,
+               "pms_dev_counters": nat.DevCounters}
+    for line in out.splitlines():
+        st, what, val = line.split()
+        cls = mirrors[st]
+        got = ctypes.sizeof(cls) if what == "size" else getattr(cls, what).offset
+        assert got == int(val), (st, what)
+
+
+def test_decode_status_and_stride():
+    assert nat.decode(0, 4) == "AAAA"
+    assert nat.decode(0b11100100, 4) == "TGCA"
+    assert nat.decode(35797, 8) == "GAGTTCCC"
+    for s, txt in [(0, "ok"), (1, "invalid argument"), (2, "output capacity exceeded"),
+                   (3, "out of memory"), (4, "device error"), (9, "unknown status")]:
+        assert nat.status_string(s) == txt
+    assert nat.window_stride(600, 15) == 592
+    assert nat.window_stride(600, 11) == 592
+    assert nat.window_stride(16, 16) == 16
+    assert nat.window_stride(17, 16) == 16
+    assert nat.window_stride(32, 16) == 32
+    assert nat.window_stride(10, 11) == 0
+    assert nat.window_stride(10, 17) == 0
+
+
+@pytest.mark.parametrize("n,t,l,d", [(0, 10, 4, 1), (65, 10, 4, 1), (3, 10, 0, 0), (3, 10, 17, 1),
+                                     (3, 3, 4, 1), (3, 10, 4, -1), (3, 10, 4, 5),
+                                     (3, (1 << 17) + 1, 4, 1)])
+def test_invalid_shapes(n, t, l, d):
+    rows = ["A" * max(min(t, 64), 1)] * max(n, 1)
+    arr = (ctypes.c_char_p * len(rows))(*[r.encode() for r in rows])
+    out = np.full(8, 0xDEADBEEF, dtype=np.uint32)
+    cnt = ctypes.c_uint64(8)
+    st = nat.lib().pms_solve(arr, n, t, l, d, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                             ctypes.byref(cnt))
+    assert st == nat.PMS_ERR_INVALID and cnt.value == 0
+    assert (out == 0xDEADBEEF).all()
+    assert nat.last_error()
+
+
+def test_invalid_pointers_and_bytes():
+    lib = nat.lib()
+    out = np.full(4, 7, dtype=np.uint32)
+    optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    cnt = ctypes.c_uint64(4)
+    assert lib.pms_solve(None, 1, 8, 4, 1, optr, ctypes.byref(cnt)) == nat.PMS_ERR_INVALID
+    assert lib.pms_solve(None, 1, 8, 4, 1, optr, None) == nat.PMS_ERR_INVALID
+    arr = (ctypes.c_char_p * 2)(b"ACGTACGT", None)
+    cnt = ctypes.c_uint64(4)
+    assert lib.pms_solve(arr, 2, 8, 4, 1, optr, ctypes.byref(cnt)) == nat.PMS_ERR_INVALID
+    assert "NULL" in nat.last_error()
+    arr = (ctypes.c_char_p * 1)(b"ACGTACGT")
+    cnt = ctypes.c_uint64(4)
+    assert lib.pms_solve(arr, 1, 8, 4, 1, None, ctypes.byref(cnt)) == nat.PMS_ERR_INVALID
+    for bad in [b"ACGTNCGT", b"ACGT-CGT", b"ACGU ACG", b"ACGT\x00CGT", b"acgtacgx"]:
+        arr = (ctypes.c_char_p * 1)(bad)
+        cnt = ctypes.c_uint64(4)
+        assert lib.pms_solve(arr, 1, 8, 4, 1, optr, ctypes.byref(cnt)) == nat.PMS_ERR_INVALID
+        assert cnt.value == 0 and (out == 7).all()
+        assert "not A/C/G/T" in nat.last_error()
+
+
+def test_solve_many_rejects_bad_batches():
+    lib = nat.lib()
+    res = (nat.Result * 1)()
+    assert lib.pms_solve_many(None, 1, res) == nat.PMS_ERR_INVALID
+    assert lib.pms_solve_many((nat.Instance * 1)(), -1, res) == nat.PMS_ERR_INVALID
+    st, motifs, results = nat.solve_many([(["ACGTNACG"], 4, 1), (["ACGT"], 5, 1)])
+    assert st == nat.PMS_ERR_INVALID
+    assert [r.status for r in results] == [nat.PMS_ERR_INVALID, nat.PMS_ERR_INVALID]
+
+
+def test_config_validation():
+    before = nat.get_config()
+    with pytest.raises(nat.PmsError):
+        nat.set_config(chunk=100)
+    with pytest.raises(nat.PmsError):
+        nat.set_config(chunk=1 << 25)
+    with pytest.raises(nat.PmsError):
+        nat.set_config(wg_waves=17)
+    with pytest.raises(nat.PmsError):
+        nat.set_config(tail_split=65)
+    assert nat.get_config() == before
+    nat.set_config(chunk=4096, wg_waves=2)
+    assert nat.get_config()["chunk"] == 4096 and nat.get_config()["wg_waves"] == 2
+    nat.set_config(reset=True)
+    assert nat.get_config() == {"chunk": 16384, "wg_waves": 4, "wgs_per_cu": 0, "tail_split": 8}
+
+
+def test_injected_failure_propagates(monkeypatch):
+    """PMS_TEST_FAIL_NEXT makes exactly the next valid call fail with that status."""
+    monkeypatch.setenv("PMS_TEST_FAIL_NEXT", str(nat.PMS_ERR_NOMEM))
+    st, cnt, _ = nat.solve_raw(["ACGTACGT"] * 2, 4, 1)
+    assert st == nat.PMS_ERR_NOMEM and cnt == 0
+    assert "injected" in nat.last_error()
+    st2, _, _ = nat.solve_raw(["ACGTACGT"] * 2, 4, 1)
+    assert st2 in (nat.PMS_OK, nat.PMS_ERR_DEVICE)  # the injection was consumed
+    monkeypatch.setenv("PMS_TEST_FAIL_NEXT", str(nat.PMS_ERR_DEVICE))
+    st, motifs, results = nat.solve_many([(["ACGTACGT"] * 2, 4, 1)])
+    assert st == nat.PMS_ERR_DEVICE
+
+
+def test_no_cpu_fallback_without_gpu():
+    """Without a GPU a valid call reports a device error; nothing is computed on the CPU."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, cnt, _ = nat.solve_raw(["ACGTACGT"] * 2, 4, 1)
+    assert st == nat.PMS_ERR_DEVICE and cnt == 0
