@@ -6,12 +6,12 @@ side only marshals arguments: see ``native`` for the binding and ``serve`` for
 the continuous-batching request server.  Nothing here falls back to a CPU
 path; importing ``native`` without the built library raises.
 """
+import importlib
 
 __all__ = ["native"]
 
 
 def __getattr__(name):
-    if name == "native":
-        from . import native
-        return native
+    if name in ("native", "serve", "benchmarks"):
+        return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

@@ -81,6 +81,14 @@ class DevCounters(ctypes.Structure):
 
 
 def _load():
+    # torch ships its own HIP runtime and its libraries ask for it by the
+    # name libamdhip64.so.  Loading torch first makes libpms.so bind to that
+    # same runtime (matched by SONAME) instead of a second copy from
+    # /opt/rocm, which would then see no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -c 'import __graft_entry__ as g; g.build()'` "

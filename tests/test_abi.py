@@ -165,3 +165,21 @@ def test_no_cpu_fallback_without_gpu():
         pytest.skip("a GPU is present")
     st, cnt, _ = nat.solve_raw(["ACGTACGT"] * 2, 4, 1)
     assert st == nat.PMS_ERR_DEVICE and cnt == 0
+
+
+def test_package_import_forms():
+    """Both import spellings work in a fresh interpreter."""
+    for stmt in ("from paper_1403_1313_amd import native; native.decode(0, 2)",
+                 "import paper_1403_1313_amd as p; p.native.decode(0, 2)",
+                 "import paper_1403_1313_amd.native as n; n.decode(0, 2)"):
+        subprocess.run([__import__("sys").executable, "-c", stmt], cwd=ROOT, check=True)
+
+
+def test_single_hip_runtime_in_process():
+    """Loading the binding before torch still maps exactly one HIP runtime."""
+    code = ("import paper_1403_1313_amd.native as n, torch\n"
+            "maps = [l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l]\n"
+            "print(len(set(maps)))\n")
+    out = subprocess.run([__import__("sys").executable, "-c", code], cwd=ROOT, check=True,
+                         capture_output=True, text=True).stdout.strip()
+    assert out == "1"
