@@ -21,8 +21,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# gfx950: 256 compute units x 4 SIMD x 16 lanes, 2.4 GHz peak engine clock.
-CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
+# gfx950 integer VALU peak: 256 compute units x 128 lane-operations per clock
+# (4 SIMDs x 32 lanes for plain 32-bit VGPR-only forms, measured with
+# pms_valu_probe; the same lane rate as the published fp32 vector figure)
+# x 2.4 GHz peak engine clock.
+CUS, LANES_PER_CU, CLOCK_HZ = 256, 128, 2.4e9
 VALU_INT32_PEAK = CUS * LANES_PER_CU * CLOCK_HZ          # lane-ops/s
 # VALU instructions per window compare in the search kernel's inner loop:
 # v_xor_b32, v_or_b32_sdwa, v_bcnt_u32_b32 and half of a v_min3_u32.
@@ -34,7 +37,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving"])
+    ap.add_argument("--mode", default="plain",
+                    choices=["plain", "batched", "serving", "probe", "copy"],
+                    help="probe: VALU issue rates; copy: a plain device copy of known size "
+                         "(calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--config", default="plain_15_4", choices=["plain_8_1", "plain_11_3", "plain_15_4"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -68,11 +75,20 @@ def cpu_baseline(seqs, l, d, target_s):
 
 
 def load_traffic(path, key):
+    """HBM bytes per launch from the counter runs, or None when the kernel
+    source has changed since they were taken."""
+    import hashlib
     try:
         with open(path) as f:
-            return json.load(f).get(key)
+            rec = json.load(f).get(key)
+        src = os.path.join(ROOT, "paper_1403_1313_amd", "csrc", "pms_kernels.hip")
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
     except (OSError, ValueError):
         return None
+    if not rec or rec.get("kernel_source_sha256_prefix") != h:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def bench_plain(args):
@@ -176,6 +192,36 @@ def bench_plain(args):
     return 0
 
 
+def bench_probe(args):
+    from paper_1403_1313_amd import native as nat
+    for op in nat.PROBE_OPS:
+        for wps in (2, 8):
+            r = nat.valu_probe(op, waves_per_simd=wps)
+            print(json.dumps({"probe": op, "waves_per_simd": wps, **r}), flush=True)
+    return 0
+
+
+def bench_copy(args):
+    """Device-to-device copy of --copy-mib MiB, --steps times (counter calibration)."""
+    import torch
+    nbytes = args.copy_mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GB_per_s_read_plus_write": 2 * nbytes / ms / 1e6}),
+          flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -184,6 +230,10 @@ def main():
         return 2
     if args.mode == "plain":
         return bench_plain(args)
+    if args.mode == "probe":
+        return bench_probe(args)
+    if args.mode == "copy":
+        return bench_copy(args)
     if args.mode == "batched":
         from paper_1403_1313_amd import benchmarks
         return benchmarks.bench_batched(args)

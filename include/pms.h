@@ -155,6 +155,40 @@ typedef struct {
 int pms_last_stats(pms_stats* out);
 
 /* ------------------------------------------------------------------------ *
+ * Measurement
+ * ------------------------------------------------------------------------ */
+
+/* Instruction kinds timed by pms_valu_probe. */
+enum pms_probe_op {
+    PMS_PROBE_XOR = 0,     /* v_xor_b32 */
+    PMS_PROBE_BCNT = 1,    /* v_bcnt_u32_b32 */
+    PMS_PROBE_MIN3 = 2,    /* v_min3_u32 */
+    PMS_PROBE_OR_SDWA = 3, /* v_or_b32_sdwa (16-bit halves) */
+    PMS_PROBE_ADD = 4,     /* v_add_u32 */
+    PMS_PROBE_FMA_F32 = 5, /* v_fma_f32, for comparison with the published fp32 rate */
+    PMS_PROBE_XOR_VV = 6,  /* v_xor_b32 with two VGPR sources */
+    PMS_PROBE_COMPARE = 7  /* the search loop's compare: xor, or_sdwa, bcnt, min3 (4 ops) */
+};
+
+typedef struct {
+    double lane_ops_per_s;           /* achieved lane-operations per second, whole GPU */
+    double ms;                       /* probe kernel time (HIP events) */
+    double sclk_mhz;                 /* engine clock during the run (shader-clock counter
+                                        over the 100 MHz real-time counter) */
+    double lane_ops_per_clk_per_cu;  /* lane_ops_per_s / (sclk * compute units) */
+    int32_t compute_units;
+    int32_t reserved;
+} pms_probe_result;
+
+/*
+ * pms_valu_probe -- issue rate of one VALU instruction kind: every lane of
+ * `waves_per_simd` x 4 wavefronts per compute unit runs 16 independent chains
+ * of the instruction for `iters` iterations (0 = defaults 8 and 32768).  Used to state the integer VALU roofline of the
+ * search kernel from measurement rather than assumption.
+ */
+int pms_valu_probe(int op, int32_t waves_per_simd, int32_t iters, pms_probe_result* out);
+
+/* ------------------------------------------------------------------------ *
  * Device level: device pointers, caller's stream (hipStream_t as void*; NULL
  * is the null stream).  Asynchronous: results are valid once the stream is
  * synchronised.  The caller owns every buffer passed in.

@@ -1,0 +1,172 @@
+"""Batched and serving measurements (``bench.py --mode batched|serving``).
+
+Both compare against the plain path run one instance per launch on the same
+GPU: ``pms_solve`` called for each instance in turn.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def _golden(name):
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)["records"]
+
+
+def _sha(codes):
+    return hashlib.sha256(np.ascontiguousarray(codes, dtype="<u4").tobytes()).hexdigest()
+
+
+def bench_batched(args):
+    import fmgen
+    from . import native as nat
+
+    specs = fmgen.batched_specs(256)
+    insts = [s.make() for s in specs]
+    work = [(i.seqs, i.l, i.d) for i in insts]
+    caps = [1 << 21] * len(insts)
+    cache = os.environ.get("PMS_AUTOTUNE_CACHE") or os.path.join(ROOT, "gpurun_out", "autotune.json")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    t0 = time.perf_counter()
+    tuned = nat.autotune(20, 650, 13, 4, cache)
+    tune_s = time.perf_counter() - t0
+
+    for _ in range(max(1, args.warmup)):
+        st, motifs, results = nat.solve_many(work, caps)
+        assert st == nat.PMS_OK, nat.last_error()
+    walls, graph_ms, lat = [], [], []
+    for _ in range(args.steps):
+        w0 = time.perf_counter()
+        st, motifs, results = nat.solve_many(work, caps)
+        walls.append(time.perf_counter() - w0)
+        assert st == nat.PMS_OK, nat.last_error()
+        s = nat.last_stats()
+        graph_ms.append(s["kernel_ms"])
+        lat.extend(r.latency_ms for r in results)
+    stats = nat.last_stats()
+
+    parity = None
+    gold = _golden("batched")
+    if gold:
+        by_seed = {r["seed"]: r for r in gold}
+        checked = 0
+        parity = True
+        for spec, m in zip(specs, motifs):
+            r = by_seed.get(spec.seed)
+            if r is None:
+                continue
+            checked += 1
+            if not (r["count"] == m.size and r["sha256"] == _sha(m)):
+                parity = False
+        parity = {"ok": parity, "instances_checked": checked}
+
+    # One instance per launch: the plain host-level path, instance by instance.
+    for i in range(3):
+        nat.solve_raw(work[i][0], work[i][1], work[i][2], capacity=caps[i])
+    p0 = time.perf_counter()
+    per_launch_ms = []
+    for (seqs, l, d), cap in zip(work, caps):
+        q0 = time.perf_counter()
+        st1, cnt, _ = nat.solve_raw(seqs, l, d, capacity=cap)
+        per_launch_ms.append((time.perf_counter() - q0) * 1e3)
+        assert st1 == nat.PMS_OK
+    plain_s = time.perf_counter() - p0
+
+    wall = float(np.median(walls))
+    cands = sum(4 ** s.l for s in specs)
+    line = {
+        "metric": "batched instances/s",
+        "value": len(specs) / wall,
+        "unit": "instances/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "256 seeded FM instances, (l,d) uniform over (9,2),(11,3),(13,4), "
+                               "n in [10,30], t in [300,1000], master seed 1403, one persistent "
+                               "launch replayed from a HIP graph", "instances": len(specs)},
+        "candidates_per_s": cands / wall,
+        "window_compares_per_s": stats["window_compares"] / wall,
+        "graph_ms_median": float(np.median(graph_ms)),
+        "instance_latency_ms_p50": _pct(lat, 50),
+        "instance_latency_ms_p99": _pct(lat, 99),
+        "total_motifs": int(sum(m.size for m in motifs)),
+        "autotuned": tuned, "autotune_s": tune_s,
+        "one_per_launch": {"total_s": plain_s, "instances_per_s": len(specs) / plain_s,
+                           "latency_ms_p50": _pct(per_launch_ms, 50),
+                           "latency_ms_p99": _pct(per_launch_ms, 99)},
+        "speedup_vs_one_per_launch": plain_s / wall,
+        "parity_vs_golden": parity,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_serving(args):
+    import fmgen
+    from . import native as nat
+    from .serve import Server
+
+    rates = [float(r) for r in os.environ.get("PMS_SERVE_RATES", "10,20,40").split(",")]
+    count = int(os.environ.get("PMS_SERVE_COUNT", "60"))
+    out = []
+    for rate in rates:
+        stream = fmgen.serving_stream(count, rate)
+        reqs = [(t_arr, spec.make()) for t_arr, spec in stream]
+        with Server(mem_budget=256 << 20) as srv:
+            # warm up the kernels and allocator
+            srv.submit(reqs[0][1].seqs, reqs[0][1].l, reqs[0][1].d).result()
+            t0 = time.perf_counter()
+            futs = []
+            for t_arr, inst in reqs:
+                now = time.perf_counter() - t0
+                if t_arr > now:
+                    time.sleep(t_arr - now)
+                futs.append(srv.submit(inst.seqs, inst.l, inst.d))
+            results = [f.result() for f in futs]
+            span = max(r.finished for r in results) - t0
+            stats = dict(srv.stats)
+        lat = [r.latency_s * 1e3 for r in results]
+        # the same arrivals served one instance per launch, first come first served
+        t1 = time.perf_counter()
+        fifo_lat = []
+        for t_arr, inst in reqs:
+            now = time.perf_counter() - t1
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            st, cnt, _ = nat.solve_raw(inst.seqs, inst.l, inst.d, capacity=1 << 21)
+            fifo_lat.append((time.perf_counter() - t1 - t_arr) * 1e3)
+        fifo_span = time.perf_counter() - t1
+        out.append({"rate": rate, "requests": count, "solves_per_s": count / span,
+                    "latency_ms_p50": _pct(lat, 50), "latency_ms_p99": _pct(lat, 99),
+                    "server_stats": stats,
+                    "one_per_launch_fifo": {"solves_per_s": count / fifo_span,
+                                            "latency_ms_p50": _pct(fifo_lat, 50),
+                                            "latency_ms_p99": _pct(fifo_lat, 99)}})
+    best = max(out, key=lambda r: r["solves_per_s"])
+    line = {
+        "metric": "served solves/s", "value": best["solves_per_s"], "unit": "solves/s",
+        "n_gpus": 1, "steps": count, "warmup": 1, "ms_per_step": 1e3 / best["solves_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "Poisson stream of seeded FM solve requests, (l,d) over "
+                               "(9,2),(11,3),(13,4),(15,4) weighted 4:3:2:1, n in [10,30], "
+                               "t in [300,1000], master seed 1313", "rates": rates},
+        "sweep": out,
+    }
+    print(json.dumps(line), flush=True)
+    return 0

@@ -13,12 +13,14 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <fstream>
 #include <mutex>
 #include <numeric>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pms.h"
@@ -557,18 +559,35 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
                           hipMemcpyDeviceToHost));
         c.last.reruns++;
     }
-    // Step a7: ascending order, then the caller's capacity.
-    for (size_t i = 0; i < m; ++i) {
-        if (status[i] != PMS_OK) continue;
-        std::vector<uint32_t>& v = host_out[i];
-        std::sort(v.begin(), v.end());
-        if (std::adjacent_find(v.begin(), v.end()) != v.end())
-            return fail(PMS_ERR_DEVICE, "duplicate motif in device output");
-        const uint64_t k = std::min<uint64_t>(caps[i], v.size());
-        if (k) memcpy(outs[i], v.data(), k * 4);
-        if (v.size() > caps[i])
+    // Step a7: ascending order, then the caller's capacity; instances are
+    // independent, so host threads take them in turn.
+    std::atomic<size_t> next{0};
+    std::atomic<bool> dup{false};
+    auto worker = [&]() {
+        for (size_t i = next++; i < m; i = next++) {
+            if (status[i] != PMS_OK) continue;
+            std::vector<uint32_t>& v = host_out[i];
+            std::sort(v.begin(), v.end());
+            if (std::adjacent_find(v.begin(), v.end()) != v.end()) {
+                dup = true;
+                continue;
+            }
+            const uint64_t k = std::min<uint64_t>(caps[i], v.size());
+            if (k) memcpy(outs[i], v.data(), k * 4);
+        }
+    };
+    uint64_t total = 0;
+    for (size_t i = 0; i < m; ++i) total += host_out[i].size();
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned nthreads = total < (1u << 16) ? 1u : std::min<unsigned>(std::min(hw, 16u), m);
+    std::vector<std::thread> pool;
+    for (unsigned w = 1; w < nthreads; ++w) pool.emplace_back(worker);
+    worker();
+    for (auto& th : pool) th.join();
+    if (dup) return fail(PMS_ERR_DEVICE, "duplicate motif in device output");
+    for (size_t i = 0; i < m; ++i)
+        if (status[i] == PMS_OK && host_out[i].size() > caps[i])
             status[i] = fail(PMS_ERR_OVERFLOW, "more motifs than capacity");
-    }
     return PMS_OK;
 }
 
@@ -983,6 +1002,45 @@ int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_p
     c.cfg = best_cfg;
     if (!path.empty()) cache_store(path, key, best_cfg);
     if (best) *best = best_cfg;
+    return PMS_OK;
+}
+
+int pms_valu_probe(int op, int32_t waves_per_simd, int32_t iters_in, pms_probe_result* out) {
+    g_last_error.clear();
+    if (!out || op < PMS_PROBE_XOR || op > PMS_PROBE_COMPARE)
+        return fail(PMS_ERR_INVALID, "bad probe op or NULL result");
+    if (waves_per_simd < 0 || waves_per_simd > 16 || iters_in < 0 || iters_in > (1 << 24))
+        return fail(PMS_ERR_INVALID, "probe size out of range");
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    PMS_TRY(init_ctx(c));
+    // 256-thread blocks are 4 wavefronts, one per SIMD when spread evenly.
+    const uint32_t blocks = static_cast<uint32_t>(c.cus) * (waves_per_simd ? waves_per_simd : 8);
+    const uint32_t iters = iters_in ? static_cast<uint32_t>(iters_in) : 32768u;
+    DevBuf sink, clocks;
+    PMS_TRY(sink.ensure(static_cast<size_t>(blocks) * 256 * 4));
+    PMS_TRY(clocks.ensure(16));
+    float ms = 0;
+    for (int rep = 0; rep < 2; ++rep) {  // the first launch warms up the clocks
+        PMS_HIP(hipEventRecord(c.ev[0], c.stream));
+        PMS_HIP(pms::valu_probe(op, blocks, iters, sink.as<uint32_t>(), clocks.as<uint64_t>(), c.stream));
+        PMS_HIP(hipEventRecord(c.ev[1], c.stream));
+        PMS_HIP(hipStreamSynchronize(c.stream));
+        PMS_HIP(hipEventElapsedTime(&ms, c.ev[0], c.ev[1]));
+    }
+    uint64_t clk[2] = {0, 0};
+    PMS_HIP(hipMemcpy(clk, clocks.p, 16, hipMemcpyDeviceToHost));
+    (void)hipFree(sink.p);
+    (void)hipFree(clocks.p);
+    const double per_chain = op == PMS_PROBE_COMPARE ? 4.0 : 1.0;
+    const double lane_ops = static_cast<double>(blocks) * 256.0 * iters * 16.0 * per_chain;
+    out->ms = ms;
+    out->lane_ops_per_s = lane_ops / (ms * 1e-3);
+    out->sclk_mhz = clk[1] ? static_cast<double>(clk[0]) / (static_cast<double>(clk[1]) * 1e-8) / 1e6 : 0;
+    out->compute_units = c.cus;
+    out->reserved = 0;
+    out->lane_ops_per_clk_per_cu =
+        out->sclk_mhz > 0 ? out->lane_ops_per_s / (out->sclk_mhz * 1e6 * c.cus) : 0;
     return PMS_OK;
 }
 

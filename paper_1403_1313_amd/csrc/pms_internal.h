@@ -35,6 +35,9 @@ hipError_t launch_fill(uint32_t* p, uint64_t words, uint32_t v, hipStream_t stre
 
 const void* search_kernel_symbol();
 
+hipError_t valu_probe(int op, uint32_t blocks, uint32_t iters, uint32_t* sink, uint64_t* clocks,
+                      hipStream_t s);
+
 // LDS words one wavefront of the search kernel needs for instances of up to
 // max_n sequences.
 inline uint32_t queue_words(int32_t max_n) {

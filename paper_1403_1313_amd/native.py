@@ -19,7 +19,10 @@ PMS_MAX_L, PMS_MAX_N, PMS_MAX_T = 16, 64, 1 << 17
 
 SYMBOLS = ["pms_solve", "pms_solve_many", "pms_decode", "pms_status_string", "pms_last_error",
            "pms_set_config", "pms_get_config", "pms_autotune", "pms_last_stats",
-           "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev"]
+           "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev",
+           "pms_valu_probe"]
+PROBE_OPS = {"xor": 0, "bcnt": 1, "min3": 2, "or_sdwa": 3, "add": 4, "fma_f32": 5, "xor_vv": 6,
+             "compare": 7}
 
 
 class PmsError(RuntimeError):
@@ -58,6 +61,12 @@ class Stats(ctypes.Structure):
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))
                 for k, t in self._fields_}
+
+
+class ProbeResult(ctypes.Structure):
+    _fields_ = [("lane_ops_per_s", ctypes.c_double), ("ms", ctypes.c_double),
+                ("sclk_mhz", ctypes.c_double), ("lane_ops_per_clk_per_cu", ctypes.c_double),
+                ("compute_units", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class DevInstance(ctypes.Structure):
@@ -111,6 +120,7 @@ def _load():
         "pms_build_windows": ([vp, i32, i32, i32, vp, vp, vp], ctypes.c_int),
         "pms_step_launch": ([vp, i32, i32, vp, i32, vp, vp, P(Config), vp], ctypes.c_int),
         "pms_solve_dev": ([vp, i32, i32, i32, i32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
+        "pms_valu_probe": ([ctypes.c_int, i32, i32, P(ProbeResult)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -229,6 +239,13 @@ def last_stats() -> dict:
     s = Stats()
     _check(_lib.pms_last_stats(ctypes.byref(s)))
     return s.as_dict()
+
+
+def valu_probe(op: str, waves_per_simd: int = 0, iters: int = 0) -> dict:
+    """Issue rate of one VALU instruction kind (see pms_valu_probe)."""
+    r = ProbeResult()
+    _check(_lib.pms_valu_probe(PROBE_OPS[op], waves_per_simd, iters, ctypes.byref(r)))
+    return {k: float(getattr(r, k)) for k, _ in r._fields_ if k != "reserved"}
 
 
 def window_stride(t: int, l: int) -> int:

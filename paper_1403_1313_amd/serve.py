@@ -1,0 +1,385 @@
+"""Continuous-batching solve server on one GPU.
+
+Requests (one planted (l, d) instance each) arrive at any time.  A request is
+admitted when its device memory (raw rows, bit-plane window table and output
+reservation) fits the memory budget; its rows are uploaded once and its
+windows built on the device, and it stays resident until it completes.
+The server then runs *steps*: each step is one persistent search launch
+(``pms_step_launch``) over work items cut from every admitted request's
+remaining candidate range, so requests that arrive while others are on the
+GPU join the next step and their work overlaps on the device.  Up to two
+steps are in flight on the server's stream.
+
+Each admitted request owns a slot in a device-resident instance table and
+state table.  Its survivors are appended to its own output buffer at its
+slot's running count, so a request's output is contiguous across steps.  When
+its last item has completed the codes are copied back and sorted; if the
+count exceeded the reservation, the request is re-run once with the exact
+capacity.  torch provides device memory, pinned staging and the stream; all
+computation runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import dataclasses
+import math
+import threading
+import time
+from typing import Deque, Dict, List, Optional
+
+import numpy as np
+
+from . import native as nat
+
+MAX_SLOTS = 1024
+ITEMS_UNTRACKED = 1 << 31  # serving does not use per-instance completion stamps
+
+
+def _estimate(l: int, d: int, n: int, t: int):
+    """(expected |M|, expected sequence scans per candidate) under uniform background."""
+    ball = sum(math.comb(l, k) * 3 ** k for k in range(d + 1))
+    p = ball / 4 ** l
+    nw = t - l + 1
+    ps = 1.0 - (1.0 - p) ** nw
+    ev = sum(ps ** k for k in range(n))
+    return 4 ** l * ps ** n + 1.0, ev
+
+
+@dataclasses.dataclass
+class Result:
+    motifs: np.ndarray          # sorted uint32 codes
+    count: int
+    arrival: float              # perf_counter seconds
+    admitted: float
+    finished: float
+    steps: int
+    reruns: int
+    visits: int
+
+    @property
+    def latency_s(self) -> float:
+        return self.finished - self.arrival
+
+
+class _Req:
+    __slots__ = ("rid", "seqs", "l", "d", "n", "t", "arrival", "future", "slot", "dev_seqs",
+                 "dev_win", "dev_out", "cap", "bytes", "total", "cursor", "inflight", "steps",
+                 "reruns", "admitted", "cost_per_cand", "stride")
+
+    def __init__(self, rid, seqs, l, d, arrival, future):
+        self.rid = rid
+        self.seqs = seqs
+        self.l, self.d = l, d
+        self.n, self.t = seqs.shape
+        self.arrival = arrival
+        self.future = future
+        self.slot = -1
+        self.dev_seqs = self.dev_win = self.dev_out = None
+        self.stride = nat.window_stride(self.t, l)
+        est_m, ev = _estimate(l, d, self.n, self.t)
+        self.cap = int(min(4 ** l, 8 * est_m + 4096))
+        self.cost_per_cand = (self.t - l + 1) * ev
+        self.total = 4 ** l
+        self.cursor = 0
+        self.inflight = 0
+        self.steps = 0
+        self.reruns = 0
+        self.admitted = 0.0
+        self.bytes = self._bytes()
+
+    def _bytes(self) -> int:
+        return self.n * self.t + self.n * self.stride * 4 + self.cap * 4
+
+
+class _StepBuf:
+    """Pinned staging and device copies of one step's tables."""
+
+    def __init__(self, torch, dev, max_items: int):
+        self.max_items = max_items
+        self.h_work = torch.zeros(max_items * 16, dtype=torch.uint8).pin_memory()
+        self.d_work = torch.zeros(max_items * 16, dtype=torch.uint8, device=dev)
+        self.d_ctr = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.h_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8).pin_memory()
+        self.event = None
+        self.reqs: List[_Req] = []
+        self.items_per_req: Dict[int, int] = {}
+
+
+class Server:
+    """Continuous-batching server.  ``submit`` returns a Future of ``Result``."""
+
+    def __init__(self, mem_budget: int = 256 << 20, step_ms: float = 3.0,
+                 chunk: int = 4096, max_inflight: int = 2, compares_per_s: float = 1.1e13,
+                 device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
+                 items_per_req: int = 96):
+        import torch
+        self.torch = torch
+        self.dev = torch.device("cuda", device)
+        torch.cuda.set_device(self.dev)
+        self.stream = torch.cuda.Stream(self.dev)
+        self.mem_budget = int(mem_budget)
+        self.step_compares = step_ms * 1e-3 * compares_per_s
+        self.chunk = int(chunk)
+        self.items_per_req = int(items_per_req)
+        self.copy_stream = torch.cuda.Stream(self.dev)
+        self.max_inflight = int(max_inflight)
+        self.config = config
+        self.reserve = reserve  # fixed first output reservation (tests of the rerun path)
+        self.d_insts = torch.zeros(MAX_SLOTS * 40, dtype=torch.uint8, device=self.dev)
+        self.d_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8, device=self.dev)
+        self.free_slots = list(range(MAX_SLOTS - 1, -1, -1))
+        self.bufs = [_StepBuf(torch, self.dev, 8192) for _ in range(max_inflight)]
+        self.idle_bufs = list(self.bufs)
+        self.inflight: Deque[_StepBuf] = collections.deque()
+        self.waiting: Deque[_Req] = collections.deque()
+        self.active: List[_Req] = []
+        self.mem_used = 0
+        self.cv = threading.Condition()
+        self.running = True
+        self.next_id = 0
+        self.error: Optional[BaseException] = None
+        self.stats = collections.Counter()
+        self.thread = threading.Thread(target=self._loop, name="pms-serve", daemon=True)
+        self.thread.start()
+
+    # ------------------------------------------------------------------ API
+    def submit(self, seqs, l: int, d: int) -> cf.Future:
+        fut: cf.Future = cf.Future()
+        m = np.ascontiguousarray(np.asarray(seqs, dtype=np.uint8))
+        try:
+            self._validate(m, l, d)
+        except nat.PmsError as e:
+            fut.set_exception(e)
+            return fut
+        with self.cv:
+            if not self.running:
+                raise RuntimeError("server is closed")
+            req = _Req(self.next_id, m, int(l), int(d), time.perf_counter(), fut)
+            if self.reserve is not None:
+                req.cap = int(self.reserve)
+                req.bytes = req._bytes()
+            self.next_id += 1
+            self.waiting.append(req)
+            self.cv.notify_all()
+        return fut
+
+    def close(self, wait: bool = True):
+        with self.cv:
+            self.running = False
+            self.cv.notify_all()
+        if wait:
+            self.thread.join()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------ internals
+    @staticmethod
+    def _validate(m: np.ndarray, l: int, d: int):
+        if m.ndim != 2 or m.shape[0] < 1:
+            raise nat.PmsError(nat.PMS_ERR_INVALID, "rows must be an (n, t) byte matrix")
+        n, t = m.shape
+        if not (1 <= n <= nat.PMS_MAX_N and 1 <= l <= nat.PMS_MAX_L and l <= t <= nat.PMS_MAX_T
+                and 0 <= d <= l):
+            raise nat.PmsError(nat.PMS_ERR_INVALID, f"size out of range n={n} t={t} l={l} d={d}")
+        ok = np.isin(m | 0x20, np.frombuffer(b"acgt", dtype=np.uint8))
+        if not ok.all():
+            raise nat.PmsError(nat.PMS_ERR_INVALID, "a byte is not A/C/G/T")
+
+    def _admit(self):
+        """Moves waiting requests in, oldest first, while memory and slots allow."""
+        torch = self.torch
+        while self.waiting and self.free_slots:
+            req = self.waiting[0]
+            if self.mem_used + req.bytes > self.mem_budget and (self.active or self.inflight):
+                self.stats["admission_waits"] += 1
+                return
+            self.waiting.popleft()
+            self._upload(req)
+            self.active.append(req)
+            self.mem_used += req.bytes
+            req.admitted = time.perf_counter()
+
+    def _upload(self, req: _Req):
+        torch = self.torch
+        req.slot = self.free_slots.pop()
+        with torch.cuda.stream(self.stream):
+            req.dev_seqs = torch.from_numpy(req.seqs.reshape(-1)).pin_memory().to(
+                self.dev, non_blocking=True)
+            req.dev_win = torch.empty(req.n * req.stride, dtype=torch.int32, device=self.dev)
+            req.dev_out = torch.empty(max(req.cap, 1), dtype=torch.int32, device=self.dev)
+        nat.build_windows(req.dev_seqs, req.n, req.t, req.l, req.dev_win, None, stream=self.stream)
+        self._write_slot(req)
+
+    def _write_slot(self, req: _Req):
+        """Device instance record and a cleared state for the request's slot."""
+        torch = self.torch
+        inst = nat.DevInstance(req.dev_win.data_ptr(), req.dev_out.data_ptr(), req.cap, req.n,
+                               req.stride, req.l, req.d)
+        st = nat.DevState(0, 0, 0, ITEMS_UNTRACKED, 0)
+        # A fresh pinned block per write; torch's pinned-memory cache keeps it
+        # alive until the asynchronous copy has run.
+        h = torch.frombuffer(bytearray(bytes(inst) + bytes(st)), dtype=torch.uint8).pin_memory()
+        with torch.cuda.stream(self.stream):
+            self.d_insts[req.slot * 40:(req.slot + 1) * 40].copy_(h[:40], non_blocking=True)
+            self.d_state[req.slot * 32:(req.slot + 1) * 32].copy_(h[40:72], non_blocking=True)
+
+    def _build_step(self, buf: _StepBuf) -> int:
+        """Fills one step's work table up to the step budget.
+
+        Shortest remaining work first (it minimises the mean latency), except
+        that the oldest admitted request is always given a quarter of the step
+        so that a long request is never starved by a stream of short ones.
+        Each request's share is cut into at most ``items_per_req`` contiguous
+        items.
+        """
+        live = [r for r in self.active if r.cursor < r.total]
+        if not live:
+            return 0
+        budget = self.step_compares
+        oldest = min(live, key=lambda r: r.arrival)
+        order = sorted(live, key=lambda r: (r.total - r.cursor) * r.cost_per_cand)
+        shares = {oldest.rid: 0.25 * budget}
+        left = 0.75 * budget
+        for r in order:
+            want = (r.total - r.cursor) * r.cost_per_cand - shares.get(r.rid, 0.0)
+            give = min(max(want, 0.0), left)
+            shares[r.rid] = shares.get(r.rid, 0.0) + give
+            left -= give
+        if left > 0:
+            shares[oldest.rid] += left
+        parts = []
+        per_req: Dict[int, int] = {}
+        used = 0
+        for r in order:
+            cands = int(shares.get(r.rid, 0.0) / r.cost_per_cand)
+            cands = max(64, (cands + 63) // 64 * 64)
+            cands = min(cands, r.total - r.cursor)
+            if cands <= 0:
+                continue
+            room = buf.max_items - used
+            if room <= 0:
+                break
+            size = max(self.chunk, -(-cands // self.items_per_req))
+            size = (size + 63) // 64 * 64
+            k = min(-(-cands // size), room)
+            begins = r.cursor + np.arange(k, dtype=np.uint64) * np.uint64(size)
+            lens = np.minimum(np.uint64(size), np.uint64(r.cursor + cands) - begins)
+            rec = np.zeros(k, dtype=[("begin", "<u8"), ("len", "<u4"), ("inst", "<u4")])
+            rec["begin"] = begins
+            rec["len"] = lens.astype(np.uint32)
+            rec["inst"] = r.slot
+            parts.append(rec)
+            r.cursor += int(lens.sum())
+            per_req[r.slot] = k
+            used += k
+        if not parts:
+            return 0
+        arr = np.concatenate(parts)
+        buf.h_work.numpy()[:arr.nbytes] = arr.view(np.uint8)
+        buf.reqs = [r for r in live if r.slot in per_req]
+        buf.items_per_req = per_req
+        return int(arr.size)
+
+    def _launch(self) -> bool:
+        if not self.idle_bufs:
+            return False
+        buf = self.idle_bufs[-1]
+        n_items = self._build_step(buf)
+        if n_items == 0:
+            return False
+        self.idle_bufs.pop()
+        torch = self.torch
+        max_n = max(r.n for r in buf.reqs)
+        with torch.cuda.stream(self.stream):
+            buf.d_work[:n_items * 16].copy_(buf.h_work[:n_items * 16], non_blocking=True)
+            buf.d_ctr.zero_()
+        nat.step_launch(self.d_insts, MAX_SLOTS, max_n, buf.d_work, n_items, self.d_state,
+                        buf.d_ctr, config=self.config, stream=self.stream)
+        with torch.cuda.stream(self.stream):
+            buf.h_state.copy_(self.d_state, non_blocking=True)
+            buf.event = torch.cuda.Event()
+            buf.event.record(self.stream)
+        for r in buf.reqs:
+            r.inflight += 1
+            r.steps += 1
+        self.inflight.append(buf)
+        self.stats["steps"] += 1
+        self.stats["items"] += n_items
+        return True
+
+    def _retire(self, buf: _StepBuf):
+        buf.event.synchronize()
+        states = np.frombuffer(buf.h_state.numpy().tobytes(), dtype=[
+            ("count", "<u8"), ("visits", "<u8"), ("t_done", "<u8"), ("items_left", "<u4"),
+            ("reserved", "<u4")])
+        for r in buf.reqs:
+            r.inflight -= 1
+            if r.cursor >= r.total and r.inflight == 0:
+                self._finish(r, int(states[r.slot]["count"]), int(states[r.slot]["visits"]),
+                             buf.event)
+        buf.reqs = []
+        self.idle_bufs.append(buf)
+
+    def _finish(self, r: _Req, count: int, visits: int, done_event):
+        torch = self.torch
+        if count > r.cap:
+            # Reservation too small: run the request again with the exact size.
+            self.mem_used -= r.bytes
+            r.cap = count
+            r.bytes = r._bytes()
+            self.mem_used += r.bytes
+            r.dev_out = torch.empty(max(r.cap, 1), dtype=torch.int32, device=self.dev)
+            r.cursor = 0
+            r.reruns += 1
+            self.stats["reruns"] += 1
+            self._write_slot(r)
+            return
+        # The request's last step has completed (done_event); copy on a side
+        # stream so the read does not wait for steps queued after it.
+        self.copy_stream.wait_event(done_event)
+        with torch.cuda.stream(self.copy_stream):
+            host = r.dev_out[:count].to("cpu", non_blocking=False) if count else None
+        codes = np.sort(host.numpy().view(np.uint32)) if count else np.zeros(0, dtype=np.uint32)
+        res = Result(codes, count, r.arrival, r.admitted, time.perf_counter(), r.steps, r.reruns,
+                     visits)
+        self.active.remove(r)
+        self.mem_used -= r.bytes
+        self.free_slots.append(r.slot)
+        r.dev_seqs = r.dev_win = r.dev_out = None
+        self.stats["completed"] += 1
+        r.future.set_result(res)
+
+    def _fail_all(self, exc: BaseException):
+        for r in list(self.active) + list(self.waiting):
+            if not r.future.done():
+                r.future.set_exception(exc)
+        self.active.clear()
+        self.waiting.clear()
+
+    def _loop(self):
+        try:
+            while True:
+                with self.cv:
+                    if not self.running and not self.waiting and not self.active and not self.inflight:
+                        return
+                    if not self.waiting and not self.active and not self.inflight:
+                        self.cv.wait(timeout=0.05)
+                        continue
+                    self._admit()
+                launched = False
+                while len(self.inflight) < self.max_inflight and self._launch():
+                    launched = True
+                if self.inflight:
+                    head = self.inflight[0]
+                    if head.event.query() or not launched:
+                        self.inflight.popleft()
+                        self._retire(head)
+        except BaseException as e:  # noqa: BLE001 - every request learns of the failure
+            self.error = e
+            with self.cv:
+                self._fail_all(e)

@@ -37,26 +37,26 @@ def sha256_codes(codes: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(codes, dtype="<u4").tobytes()).hexdigest()
 
 
-def record(spec: fmgen.Spec, mode: str, threads: int) -> dict:
+def record(spec: fmgen.Spec, mode: str, threads: int, max_listed: int = MAX_LISTED) -> dict:
     inst = spec.make()
     t0 = time.time()
-    motifs = oracle.solve(inst.seqs, spec.l, spec.d, mode=mode, threads=threads,
-                          cap=1 << 26)
-    dt = time.time() - t0
     if mode == "skip":
-        skip_motifs, visits = oracle.solve(inst.seqs, spec.l, spec.d, mode="skip",
-                                           threads=threads, cap=1 << 26, return_visits=True)
+        motifs, visits = oracle.solve(inst.seqs, spec.l, spec.d, mode="skip", threads=threads,
+                                      cap=1 << 26, return_visits=True)
+        dt = time.time() - t0
     else:
+        motifs = oracle.solve(inst.seqs, spec.l, spec.d, mode=mode, threads=threads, cap=1 << 26)
+        dt = time.time() - t0
         skip_motifs, visits = oracle.solve(inst.seqs, spec.l, spec.d, mode="skip",
                                            threads=threads, cap=1 << 26, return_visits=True)
-    if not np.array_equal(skip_motifs, motifs):
-        raise AssertionError(f"skip and {mode} disagree on {spec}")
+        if not np.array_equal(skip_motifs, motifs):
+            raise AssertionError(f"skip and {mode} disagree on {spec}")
     rec = dict(l=spec.l, d=spec.d, n=spec.n, t=spec.t, seed=spec.seed,
                generator=fmgen.GENERATOR_VERSION, mode=mode,
                count=int(motifs.size), sha256=sha256_codes(motifs),
                skip_visits=int(visits), consensus=inst.consensus,
                oracle_seconds=round(dt, 2), oracle_threads=threads)
-    if motifs.size <= MAX_LISTED:
+    if motifs.size <= max_listed:
         rec["motifs"] = [oracle.number_to_lmer(int(k), spec.l) for k in motifs]
     return rec
 
@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--mode", default="brute", choices=["brute", "skip"])
     ap.add_argument("--threads", type=int, default=os.cpu_count())
     ap.add_argument("--count", type=int, default=256, help="batched: number of instances")
+    ap.add_argument("--max-listed", type=int, default=None,
+                    help="list motifs only up to this count (default 4096, batched 64)")
     args = ap.parse_args()
     for cfg in args.configs:
         path = os.path.join(HERE, f"{cfg}.json")
@@ -86,7 +88,9 @@ def main():
             key = (spec.seed, spec.l, spec.d, spec.n, spec.t)
             if key in old and (old[key]["mode"] == "brute" or args.mode == "skip"):
                 continue
-            rec = record(spec, args.mode, args.threads)
+            listed = args.max_listed if args.max_listed is not None else (
+                64 if cfg == "batched" else MAX_LISTED)
+            rec = record(spec, args.mode, args.threads, listed)
             old[key] = rec
             print(f"{cfg} #{q} l={spec.l} d={spec.d} n={spec.n} t={spec.t} "
                   f"count={rec['count']} {rec['oracle_seconds']}s", flush=True)

@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 13
+    assert len(names) == 14
     assert sorted(nat.SYMBOLS) == names
     lib = ctypes.CDLL(nat.LIB_PATH)
     for name in names:
@@ -43,6 +43,8 @@ def test_struct_layouts_match_header(tmp_path):
         "pms_work_item": ["begin", "len", "inst"],
         "pms_dev_state": ["count", "visits", "t_done", "items_left"],
         "pms_dev_counters": ["next_item", "error", "batches", "t_start"],
+        "pms_probe_result": ["lane_ops_per_s", "ms", "sclk_mhz", "lane_ops_per_clk_per_cu",
+                             "compute_units"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pms.h"', "int main(void){"]
     for st, fs in fields.items():
@@ -57,7 +59,7 @@ def test_struct_layouts_match_header(tmp_path):
     mirrors = {"pms_instance": nat.Instance, "pms_result": nat.Result, "pms_config": nat.Config,
                "pms_stats": nat.Stats, "pms_dev_instance": nat.DevInstance,
                "pms_work_item": nat.WorkItem, "pms_dev_state": nat.DevState,
-               "pms_dev_counters": nat.DevCounters}
+               "pms_dev_counters": nat.DevCounters, "pms_probe_result": nat.ProbeResult}
     for line in out.splitlines():
         st, what, val = line.split()
         cls = mirrors[st]
