@@ -110,9 +110,9 @@ class Server:
     """Continuous-batching server.  ``submit`` returns a Future of ``Result``."""
 
     def __init__(self, mem_budget: int = 256 << 20, step_ms: float = 3.0,
-                 chunk: int = 4096, max_inflight: int = 2, compares_per_s: float = 1.1e13,
+                 max_inflight: int = 2, compares_per_s: float = 1.1e13,
                  device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
-                 items_per_req: int = 96):
+                 items_per_step: int = 8192):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)
@@ -120,8 +120,7 @@ class Server:
         self.stream = torch.cuda.Stream(self.dev)
         self.mem_budget = int(mem_budget)
         self.step_compares = step_ms * 1e-3 * compares_per_s
-        self.chunk = int(chunk)
-        self.items_per_req = int(items_per_req)
+        self.items_per_step = int(items_per_step)
         self.copy_stream = torch.cuda.Stream(self.dev)
         self.max_inflight = int(max_inflight)
         self.config = config
@@ -129,7 +128,7 @@ class Server:
         self.d_insts = torch.zeros(MAX_SLOTS * 40, dtype=torch.uint8, device=self.dev)
         self.d_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8, device=self.dev)
         self.free_slots = list(range(MAX_SLOTS - 1, -1, -1))
-        self.bufs = [_StepBuf(torch, self.dev, 8192) for _ in range(max_inflight)]
+        self.bufs = [_StepBuf(torch, self.dev, 2 * self.items_per_step) for _ in range(max_inflight)]
         self.idle_bufs = list(self.bufs)
         self.inflight: Deque[_StepBuf] = collections.deque()
         self.waiting: Deque[_Req] = collections.deque()
@@ -232,10 +231,11 @@ class Server:
         """Fills one step's work table up to the step budget.
 
         Shortest remaining work first (it minimises the mean latency), except
-        that the oldest admitted request is always given a quarter of the step
+        that the oldest admitted request is always given half of the step
         so that a long request is never starved by a stream of short ones.
-        Each request's share is cut into at most ``items_per_req`` contiguous
-        items.
+        Shares are cut into items of about ``step_compares / items_per_step``
+        window compares each, so every step offers a few items per resident
+        wavefront whatever the request sizes are.
         """
         live = [r for r in self.active if r.cursor < r.total]
         if not live:
@@ -243,8 +243,8 @@ class Server:
         budget = self.step_compares
         oldest = min(live, key=lambda r: r.arrival)
         order = sorted(live, key=lambda r: (r.total - r.cursor) * r.cost_per_cand)
-        shares = {oldest.rid: 0.25 * budget}
-        left = 0.75 * budget
+        shares = {oldest.rid: 0.5 * budget}
+        left = 0.5 * budget
         for r in order:
             want = (r.total - r.cursor) * r.cost_per_cand - shares.get(r.rid, 0.0)
             give = min(max(want, 0.0), left)
@@ -252,6 +252,7 @@ class Server:
             left -= give
         if left > 0:
             shares[oldest.rid] += left
+        item_compares = budget / self.items_per_step
         parts = []
         per_req: Dict[int, int] = {}
         used = 0
@@ -264,8 +265,8 @@ class Server:
             room = buf.max_items - used
             if room <= 0:
                 break
-            size = max(self.chunk, -(-cands // self.items_per_req))
-            size = (size + 63) // 64 * 64
+            size = int(item_compares / r.cost_per_cand)
+            size = max(64, (size + 63) // 64 * 64)
             k = min(-(-cands // size), room)
             begins = r.cursor + np.arange(k, dtype=np.uint64) * np.uint64(size)
             lens = np.minimum(np.uint64(size), np.uint64(r.cursor + cands) - begins)

@@ -134,7 +134,7 @@ def test_serving_results_alone_and_in_the_mix(nat):
     from paper_1403_1313_amd.serve import Server
     batch = mixed_batch()
     want = oracle_sets(batch)
-    with Server(mem_budget=64 << 20, step_ms=0.5, chunk=4096) as srv:
+    with Server(mem_budget=64 << 20, step_ms=0.5) as srv:
         alone = [srv.submit(*b).result(timeout=120) for b in batch]
         futs = [srv.submit(*b) for b in batch]
         mixed = [f.result(timeout=120) for f in futs]
@@ -150,7 +150,7 @@ def test_serving_tiny_budget_queues_but_completes(nat):
     from paper_1403_1313_amd.serve import Server
     batch = mixed_batch()[:6]
     want = oracle_sets(batch)
-    with Server(mem_budget=1, step_ms=0.5, chunk=4096) as srv:
+    with Server(mem_budget=1, step_ms=0.5) as srv:
         futs = [srv.submit(*b) for b in batch]
         got = [f.result(timeout=120) for f in futs]
         assert srv.stats["admission_waits"] >= 1
@@ -162,7 +162,7 @@ def test_serving_overflow_reruns(nat):
     from paper_1403_1313_amd.serve import Server
     batch = mixed_batch()[-3:]
     want = oracle_sets(batch)
-    with Server(mem_budget=64 << 20, reserve=1, chunk=4096) as srv:
+    with Server(mem_budget=64 << 20, reserve=1) as srv:
         got = [srv.submit(*b).result(timeout=120) for b in batch]
         assert srv.stats["reruns"] >= 1
     for g, w in zip(got, want):
