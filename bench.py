@@ -27,9 +27,11 @@ sys.path.insert(0, ROOT)
 # x 2.4 GHz peak engine clock.
 CUS, LANES_PER_CU, CLOCK_HZ = 256, 128, 2.4e9
 VALU_INT32_PEAK = CUS * LANES_PER_CU * CLOCK_HZ          # lane-ops/s
-# VALU instructions per window compare in the search kernel's inner loop:
-# v_xor_b32, v_or_b32_sdwa, v_bcnt_u32_b32 and half of a v_min3_u32.
-OPS_PER_COMPARE = 3.5
+# Per-lane kernel: VALU instructions per window compare in its inner loop
+# (v_xor_b32, v_or_b32_sdwa, v_bcnt_u32_b32 and half of a v_min3_u32).
+LANE_OPS_PER_COMPARE = 3.5
+KERNELS = {1: ("pms_search_kernel", "pms_kernels.hip"),
+           2: ("pms_search_group_kernel", "pms_group.hip")}
 
 
 def parse():
@@ -44,11 +46,13 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--config", default="plain_15_4", choices=["plain_8_1", "plain_11_3", "plain_15_4"])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--variant", default="auto", choices=["auto", "lane", "group"],
+                    help="search kernel variant")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="HBM bytes per launch measured by rocprofv3 counters")
+    ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "counters.json"),
+                    help="rocprofv3 counter results per kernel and workload")
     return ap.parse_args()
 
 
@@ -74,21 +78,19 @@ def cpu_baseline(seqs, l, d, target_s):
                       f"({span / 4 ** l:.2e} of 4^{l}), {dt:.1f} s on {threads} host threads"}
 
 
-def load_traffic(path, key):
-    """HBM bytes per launch from the counter runs, or None when the kernel
-    source has changed since they were taken."""
+def load_counters(path, key, source):
+    """Counter record for `key` and whether the kernel source still matches it."""
     import hashlib
     try:
         with open(path) as f:
             rec = json.load(f).get(key)
-        src = os.path.join(ROOT, "paper_1403_1313_amd", "csrc", "pms_kernels.hip")
-        with open(src, "rb") as f:
+        with open(os.path.join(ROOT, "paper_1403_1313_amd", "csrc", source), "rb") as f:
             h = hashlib.sha256(f.read()).hexdigest()[:16]
     except (OSError, ValueError):
-        return None
-    if not rec or rec.get("kernel_source_sha256_prefix") != h:
-        return None
-    return rec["bytes_per_launch"]
+        return None, False
+    if not rec:
+        return None, False
+    return rec, rec.get("kernel_source_sha256_prefix") == h
 
 
 def bench_plain(args):
@@ -96,6 +98,7 @@ def bench_plain(args):
     import fmgen
     from paper_1403_1313_amd import native as nat
 
+    nat.set_config(variant={"auto": 0, "lane": 1, "group": 2}[args.variant])
     shape = fmgen.PLAIN[args.config]
     inst = fmgen.gen_fm(seed=args.seed, **shape)
     l, d, n, t = inst.l, inst.d, inst.n, inst.t
@@ -135,7 +138,17 @@ def bench_plain(args):
     cands = 4 ** l
     k_ms = float(np.mean(kernel_ms))
     wc = st["window_compares"]
-    achieved = wc * OPS_PER_COMPARE / (k_ms * 1e-3)
+    kname, ksrc = KERNELS[st["variant"]]
+    rec, fresh = load_counters(args.counters, f"{kname}/{args.config}", ksrc)
+    if st["variant"] == 1:
+        opc, opc_src = LANE_OPS_PER_COMPARE, "inner-loop ISA: 56 VALU per 16 windows"
+    elif rec:
+        # executed VALU lane-operations per algorithmic compare (SQ_INSTS_VALU x 64 / W)
+        opc = rec["valu_insts_per_launch"] * 64 / rec["window_compares"]
+        opc_src = "SQ_INSTS_VALU x 64 / window compares" + ("" if fresh else " (kernel changed since)")
+    else:
+        opc, opc_src = None, "no counter run for this kernel"
+    achieved = wc * opc / (k_ms * 1e-3) if opc else None
 
     parity = None
     gpath = os.path.join(ROOT, "tests", "golden", f"{args.config}.json")
@@ -146,7 +159,7 @@ def bench_plain(args):
             parity = [nat.decode(int(c), l) for c in codes] == recs[0]["motifs"] and \
                 st["seq_visits"] == recs[0]["skip_visits"]
 
-    traffic = load_traffic(args.traffic, f"pms_search_kernel/{args.config}")
+    traffic = rec["bytes_per_launch"] if (rec and fresh) else None
     line = {
         "metric": "candidates/s",
         "value": cands / (ms_step * 1e-3),
@@ -169,20 +182,22 @@ def bench_plain(args):
         "wall_ms_per_step": wall * 1e3 / args.steps,
         "seq_visits": st["seq_visits"],
         "window_compares": wc,
-        "executed_lane_scans": st["batches"] * 64,
-        "lane_efficiency": st["seq_visits"] / max(1, st["batches"] * 64),
+        "candidate_slots": st["candidate_slots"],
+        "slot_efficiency": st["seq_visits"] / max(1, st["candidate_slots"]),
+        "variant": {1: "lane", 2: "group"}[st["variant"]],
         "motifs": int(codes.size),
         "parity_vs_golden": parity,
         "launch": {"grid": st["grid"], "wg_waves": st["wg_waves"], "chunk": st["chunk"]},
         "roofline": {
             "bound": "alu",
-            "achieved": achieved / 1e12,
+            "achieved": achieved / 1e12 if achieved else None,
             "peak": VALU_INT32_PEAK / 1e12,
             "unit": "Tops/s",
-            "frac": achieved / VALU_INT32_PEAK,
+            "frac": achieved / VALU_INT32_PEAK if achieved else None,
             "traffic": traffic,
-            "kernel": "pms_search_kernel",
-            "ops_per_compare": OPS_PER_COMPARE,
+            "kernel": kname,
+            "ops_per_compare": opc,
+            "ops_per_compare_source": opc_src,
         },
         "cpu_baseline": None,
     }

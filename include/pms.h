@@ -111,6 +111,22 @@ const char* pms_last_error(void);
  * Launch configuration and tuning
  * ------------------------------------------------------------------------ */
 
+/* Search kernel variants (pms_config.variant). */
+enum pms_variant {
+    PMS_VARIANT_AUTO = 0,  /* GROUP when every instance of a launch has l >= 2, else LANE */
+    PMS_VARIANT_LANE = 1,  /* one candidate per lane; per window v_xor + v_or_b32_sdwa +
+                              v_bcnt + v_min3 (bit-plane window layout) */
+    PMS_VARIANT_GROUP = 2  /* 16 candidates sharing l-2 bases per lane; 32 windows per
+                              register, carry-save counts (bit-sliced window layout) */
+};
+
+/* Window table layouts (pms_build_windows). */
+enum pms_layout {
+    PMS_LAYOUT_PLANES = 0,    /* [row][window] uint32: high plane << 16 | low plane */
+    PMS_LAYOUT_BITSLICED = 1  /* [row][group of 32 windows][2l] uint32: word p has bit j =
+                                 high bit of base p of window 32g+j, word l+p the low bit */
+};
+
 /* Shape of the persistent search launch.  Zero fields mean "default". */
 typedef struct {
     uint32_t chunk;        /* candidates per work item (multiple of 64) */
@@ -118,6 +134,7 @@ typedef struct {
     uint32_t wgs_per_cu;   /* resident workgroups per compute unit (0 = as many as fit) */
     uint32_t tail_split;   /* work items of the last tail_split/64 of each instance are
                               cut 4x smaller, so the launch ends evenly (0..64) */
+    uint32_t variant;      /* pms_variant */
 } pms_config;
 
 /* Sets the configuration used by later calls that pass no configuration
@@ -144,12 +161,16 @@ typedef struct {
     uint64_t seq_visits;     /* (candidate, sequence) scans = algorithmic work of the
                                 enhanced rule; times the window count it is the
                                 algorithmic window-compare count */
-    uint64_t batches;        /* 64-lane sequence scans executed */
+    uint64_t batches;        /* wavefront sequence scans executed */
     uint64_t window_compares;/* sum over instances of seq_visits x (t-l+1) */
+    uint64_t candidate_slots;/* candidate scan slots executed: batches x 64 (LANE) or
+                                batches x 64 x 16 (GROUP) */
     uint32_t grid;           /* workgroups launched */
     uint32_t wg_waves;
     uint32_t chunk;
     uint32_t reruns;         /* relaunches caused by device output overflow */
+    uint32_t variant;        /* pms_variant actually launched (LANE or GROUP) */
+    uint32_t reserved;
 } pms_stats;
 
 int pms_last_stats(pms_stats* out);
@@ -194,33 +215,38 @@ int pms_valu_probe(int op, int32_t waves_per_simd, int32_t iters, pms_probe_resu
  * synchronised.  The caller owns every buffer passed in.
  * ------------------------------------------------------------------------ */
 
-/* Number of uint32 window slots per sequence row for length t and motif
- * length l: t-l+1 rounded up to a multiple of 16 (0 for invalid sizes). */
-int32_t pms_window_stride(int32_t t, int32_t l);
+/* Number of uint32 words per sequence row of a window table for length t,
+ * motif length l and `layout`: PLANES, t-l+1 rounded up to a multiple of 16;
+ * BITSLICED, 2l per group of 32 windows (0 for invalid sizes, and for
+ * BITSLICED with l < 2). */
+int32_t pms_window_stride(int32_t t, int32_t l, int32_t layout);
 
 /*
  * pms_build_windows -- steps a1+a2: encodes n rows of t bytes (row-major at
  * dev_seqs, device memory) into 2-bit codes, stages each row in LDS, and
- * writes every window of length l in bit-plane form to
- * dev_windows[n][pms_window_stride(t, l)] (high-bit plane of base p in bit
- * 16 + l-1-p, low-bit plane in bit l-1-p; padding slots repeat window 0).
- * Bytes that are not A/C/G/T (either case) set *dev_bad (device uint32) to 1;
- * dev_bad may be NULL.
+ * writes every window of length l to dev_windows[n][pms_window_stride(t, l,
+ * layout)].  PLANES: window j is (high-bit plane of base p in bit 16+l-1-p,
+ * low-bit plane in bit l-1-p).  BITSLICED: see pms_layout.  Window slots past
+ * t-l+1 repeat window 0.  Bytes that are not A/C/G/T (either case) set
+ * *dev_bad (device uint32) to 1; dev_bad may be NULL.
  */
-int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l,
+int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t layout,
                       uint32_t* dev_windows, uint32_t* dev_bad, void* stream);
 
 /* Device-resident description of one instance for pms_step_launch. */
 typedef struct {
-    const uint32_t* windows; /* [n][nw_stride] from pms_build_windows */
+    const uint32_t* windows; /* [n][nw_stride] from pms_build_windows, in the layout of
+                                the launch's variant (LANE: PLANES, GROUP: BITSLICED) */
     uint32_t* out;           /* motif codes, unsorted, up to out_cap of them */
     uint64_t out_cap;
     int32_t n, nw_stride, l, d;
 } pms_dev_instance;
 
-/* One work item: candidates [begin, begin+len) of instance `inst`, numbered
- * in bit-plane order (candidate k has high plane k >> l and low plane
- * k & (2^l - 1)).  len is at most 2^31. */
+/* One work item: candidates [begin, begin+len) of instance `inst`.  LANE
+ * numbers candidates in bit-plane order (candidate k has high plane k >> l and
+ * low plane k & (2^l - 1)); GROUP in dictionary order (k is the motif code),
+ * and there begin and len must be multiples of 16.  Either way the items of
+ * an instance must cover [0, 4^l) once.  len is at most 2^31. */
 typedef struct {
     uint64_t begin;
     uint32_t len;
@@ -249,8 +275,11 @@ typedef struct {
  * pms_step_launch -- steps a3-a6: one persistent search launch over the
  * work items dev_work[0 .. n_work).  Each instance's survivors are appended
  * (unsorted, as motif codes) to its `out`; its state counts them.  cfg may be
- * NULL (current configuration).  n_inst/n_work are the table lengths;
- * max_n is the largest n over the instances (it sizes LDS).
+ * NULL (current configuration); its variant selects the kernel and so the
+ * window layout the instances must have (AUTO means GROUP here).
+ * n_inst/n_work are the table lengths; max_n is the largest n over the
+ * instances the items reference (it sizes LDS; an instance with more
+ * sequences is refused and sets the counters' error flag).
  */
 int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32_t max_n,
                     const pms_work_item* dev_work, int32_t n_work,

@@ -114,12 +114,14 @@ pms_config default_config() {
     c.wg_waves = 4;
     c.wgs_per_cu = 0;
     c.tail_split = 8;
+    c.variant = PMS_VARIANT_AUTO;
     return c;
 }
 
 bool config_ok(const pms_config& c) {
     return c.chunk >= 64 && c.chunk % 64 == 0 && c.chunk <= (1u << 24) && c.wg_waves >= 1 &&
-           c.wg_waves <= 16 && c.wgs_per_cu <= 64 && c.tail_split <= 64;
+           c.wg_waves <= 16 && c.wgs_per_cu <= 64 && c.tail_split <= 64 &&
+           c.variant <= PMS_VARIANT_GROUP;
 }
 
 pms_config resolve(const pms_config* c, const pms_config& cur) {
@@ -161,9 +163,12 @@ int validate_rows(const char* const* seqs, int32_t n, int32_t t) {
     return PMS_OK;
 }
 
-int32_t window_stride(int32_t t, int32_t l) {
+int32_t window_stride(int32_t t, int32_t l, int32_t layout) {
     if (l < 1 || t < l) return 0;
-    return static_cast<int32_t>(align_up(static_cast<size_t>(t - l + 1), 16));
+    const size_t nw = static_cast<size_t>(t - l + 1);
+    if (layout == PMS_LAYOUT_PLANES) return static_cast<int32_t>(align_up(nw, 16));
+    if (l < 2) return 0;
+    return static_cast<int32_t>((nw + 31) / 32 * 2 * l);
 }
 
 // Probability that a uniform random window lies within d of a fixed l-mer,
@@ -219,6 +224,7 @@ struct Batch {
     std::vector<uint32_t> items_per_inst;
     size_t raw_bytes = 0, win_words = 0, out_words = 0;
     int32_t max_n = 1, max_t = 1;
+    bool group = false;  // GROUP variant (bit-sliced layout) for this launch
     // meta layout (bytes) inside d_meta / h_meta
     size_t off_insts = 0, off_jobs = 0, off_work = 0, off_state = 0, off_ctr = 0, off_bad = 0,
            meta_bytes = 0;
@@ -251,6 +257,7 @@ struct Ctx {
     size_t dv_state_off = 0, dv_ctr_off = 0;
     int32_t dv_nw = 0;
     bool dv_counters = false;
+    bool dv_group = false;
 };
 
 Ctx g_ctx;
@@ -280,17 +287,17 @@ int init_ctx(Ctx& c) {
 }
 
 // Workgroup shape and grid for a search launch.
-int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t* grid,
+int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, bool group, uint32_t* grid,
                  uint32_t* waves, uint32_t* q_words) {
-    const uint32_t qw = pms::queue_words(max_n);
+    const uint32_t qw = pms::queue_words(max_n, group);
     const size_t per_wave = static_cast<size_t>(qw + PMS_OUTBUF) * sizeof(uint32_t);
     uint32_t w = cfg.wg_waves;
     while (w > 1 && per_wave * w > c.lds_per_block) --w;
     if (per_wave * w > c.lds_per_block)
         return fail(PMS_ERR_INVALID, "stage queues exceed the LDS of one workgroup");
     int per_cu = 0;
-    PMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(pms::search_kernel_symbol()), 64 * w, per_wave * w));
+    const void* fn = group ? pms::search_group_kernel_symbol() : pms::search_kernel_symbol();
+    PMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * w, per_wave * w));
     if (per_cu < 1) per_cu = 1;
     if (cfg.wgs_per_cu > 0 && static_cast<int>(cfg.wgs_per_cu) < per_cu) per_cu = cfg.wgs_per_cu;
     *grid = static_cast<uint32_t>(per_cu * c.cus);
@@ -334,10 +341,14 @@ void plan_batch(Batch& b, const pms_config& cfg) {
     b.raw_bytes = b.win_words = b.out_words = 0;
     b.max_n = 1;
     b.max_t = 1;
+    b.group = cfg.variant != PMS_VARIANT_LANE;
+    for (size_t i = 0; i < m; ++i)
+        if (b.shape[i].l < 2) b.group = false;
+    const int32_t layout = b.group ? PMS_LAYOUT_BITSLICED : PMS_LAYOUT_PLANES;
     std::vector<double> cost(m);
     for (size_t i = 0; i < m; ++i) {
         const Shape& s = b.shape[i];
-        const int32_t stride = window_stride(s.t, s.l);
+        const int32_t stride = window_stride(s.t, s.l, layout);
         b.raw_off[i] = b.raw_bytes;
         b.win_off[i] = b.win_words;
         b.out_off[i] = b.out_words;
@@ -345,7 +356,7 @@ void plan_batch(Batch& b, const pms_config& cfg) {
         for (int32_t r = 0; r < s.n; ++r)
             b.jobs.push_back({b.raw_off[i] + static_cast<size_t>(r) * s.t,
                               b.win_off[i] + static_cast<size_t>(r) * stride, s.t, s.l, stride,
-                              static_cast<int32_t>(i)});
+                              static_cast<int32_t>(i), layout, 0});
         b.raw_bytes += align_up(static_cast<size_t>(s.n) * s.t, 256);
         b.win_words += static_cast<size_t>(s.n) * stride;
         b.out_words += align_up(b.out_cap[i], 64);
@@ -397,7 +408,7 @@ int stage_batch(Ctx& c, Batch& b) {
         insts[i].out = c.d_out.as<uint32_t>() + b.out_off[i];
         insts[i].out_cap = b.out_cap[i];
         insts[i].n = s.n;
-        insts[i].nw_stride = window_stride(s.t, s.l);
+        insts[i].nw_stride = window_stride(s.t, s.l, b.group ? PMS_LAYOUT_BITSLICED : PMS_LAYOUT_PLANES);
         insts[i].l = s.l;
         insts[i].d = s.d;
         state[i].items_left = b.items_per_inst[i];
@@ -419,12 +430,11 @@ int enqueue_batch(Ctx& c, const Batch& b, bool timed, uint32_t grid, uint32_t wa
                                 c.d_raw.as<uint8_t>(), c.d_win.as<uint32_t>(),
                                 reinterpret_cast<uint32_t*>(dm + b.off_bad), c.stream));
     if (timed) PMS_HIP(hipEventRecord(c.ev[1], c.stream));
-    PMS_HIP(pms::launch_search(reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
-                               reinterpret_cast<const pms_work_item*>(dm + b.off_work),
-                               static_cast<uint32_t>(b.work.size()),
-                               reinterpret_cast<pms_dev_state*>(dm + b.off_state),
-                               reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves,
-                               c.stream));
+    PMS_HIP((b.group ? pms::launch_search_group : pms::launch_search)(
+        reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
+        reinterpret_cast<const pms_work_item*>(dm + b.off_work), static_cast<uint32_t>(b.work.size()),
+        reinterpret_cast<pms_dev_state*>(dm + b.off_state),
+        reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves, c.stream));
     if (timed) PMS_HIP(hipEventRecord(c.ev[2], c.stream));
     PMS_HIP(hipMemcpyAsync(c.h_back.as<char>(b.off_state), dm + b.off_state,
                            b.meta_bytes - b.off_state, hipMemcpyDeviceToHost, c.stream));
@@ -438,14 +448,14 @@ std::string graph_signature(const Ctx& c, const Batch& b, const pms_config& cfg)
       << b.meta_bytes << ':' << b.off_state << ':' << b.jobs.size() << ':' << b.work.size()
       << ':' << b.max_n << ':' << b.max_t << ':' << cfg.chunk << ':' << cfg.wg_waves << ':'
       << cfg.wgs_per_cu << ':' << b.shape.size() << ':' << b.off_insts << ':' << b.off_jobs << ':'
-      << b.off_work << ':' << b.off_ctr << ':' << b.off_bad;
+      << b.off_work << ':' << b.off_ctr << ':' << b.off_bad << ':' << b.group;
     return o.str();
 }
 
 // Runs a staged batch: eagerly (timed with events) or through the graph.
 int run_batch(Ctx& c, Batch& b, const pms_config& cfg, bool use_graph) {
     uint32_t grid = 0, waves = 0, qw = 0;
-    PMS_TRY(launch_shape(c, cfg, b.max_n, &grid, &waves, &qw));
+    PMS_TRY(launch_shape(c, cfg, b.max_n, b.group, &grid, &waves, &qw));
     if (use_graph) {
         const std::string sig = graph_signature(c, b, cfg);
         if (!c.gexec || sig != c.gsig) {
@@ -487,6 +497,7 @@ int run_batch(Ctx& c, Batch& b, const pms_config& cfg, bool use_graph) {
     c.last.grid = grid;
     c.last.wg_waves = waves;
     c.last.chunk = cfg.chunk;
+    c.last.variant = b.group ? PMS_VARIANT_GROUP : PMS_VARIANT_LANE;
     c.last_pending = false;
     return PMS_OK;
 }
@@ -533,6 +544,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     c.last.seq_visits = visits;
     c.last.window_compares = wcmp;
     c.last.batches = ctr->batches;
+    c.last.candidate_slots = ctr->batches * 64u * (b.group ? 16u : 1u);
     c.last.reruns = 0;
     // Outputs larger than the device estimate: solve those again with the
     // exact capacity (the count is exact, so one rerun suffices).
@@ -626,12 +638,13 @@ std::vector<std::string> synthetic_rows(int32_t n, int32_t t, int32_t l, int32_t
 
 std::string tune_key(const Ctx& c, int32_t n, int32_t t, int32_t l, int32_t d) {
     std::ostringstream o;
-    o << c.arch << "/cu" << c.cus << "/l" << l << "/d" << d << "/n" << n << "/nw"
-      << align_up(static_cast<size_t>(t - l + 1), 128);
+    o << c.arch << "/cu" << c.cus << "/v" << c.cfg.variant << "/l" << l << "/d" << d << "/n" << n
+      << "/nw" << align_up(static_cast<size_t>(t - l + 1), 128);
     return o.str();
 }
 
-// The cache file is one flat JSON object: {"key": [chunk, wg_waves, wgs_per_cu, tail], ...}
+// The cache file is one flat JSON object:
+// {"key": [chunk, wg_waves, wgs_per_cu, tail_split, variant], ...}
 bool cache_lookup(const std::string& path, const std::string& key, pms_config* out) {
     std::ifstream f(path);
     if (!f) return false;
@@ -641,9 +654,10 @@ bool cache_lookup(const std::string& path, const std::string& key, pms_config* o
     const std::string pat = "\"" + key + "\": [";
     const size_t p = s.find(pat);
     if (p == std::string::npos) return false;
-    unsigned a = 0, b = 0, cc = 0, dd = 0;
-    if (sscanf(s.c_str() + p + pat.size(), "%u, %u, %u, %u", &a, &b, &cc, &dd) != 4) return false;
-    pms_config r{a, b, cc, dd};
+    unsigned a = 0, b = 0, cc = 0, dd = 0, ee = 0;
+    if (sscanf(s.c_str() + p + pat.size(), "%u, %u, %u, %u, %u", &a, &b, &cc, &dd, &ee) != 5)
+        return false;
+    pms_config r{a, b, cc, dd, ee};
     if (!config_ok(r)) return false;
     *out = r;
     return true;
@@ -665,7 +679,8 @@ void cache_store(const std::string& path, const std::string& key, const pms_conf
         }
     }
     std::ostringstream v;
-    v << cfg.chunk << ", " << cfg.wg_waves << ", " << cfg.wgs_per_cu << ", " << cfg.tail_split;
+    v << cfg.chunk << ", " << cfg.wg_waves << ", " << cfg.wgs_per_cu << ", " << cfg.tail_split << ", "
+      << cfg.variant;
     entries.emplace_back(key, v.str());
     std::ofstream f(path + ".tmp");
     f << "{\n";
@@ -702,9 +717,10 @@ void pms_decode(uint32_t code, int32_t l, char* out) {
     for (int32_t p = 0; p < l; ++p) out[p] = "ACGT"[(code >> (2 * (l - 1 - p))) & 3u];
 }
 
-int32_t pms_window_stride(int32_t t, int32_t l) {
+int32_t pms_window_stride(int32_t t, int32_t l, int32_t layout) {
     if (l < 1 || l > PMS_MAX_L || t < l || t > PMS_MAX_T) return 0;
-    return window_stride(t, l);
+    if (layout != PMS_LAYOUT_PLANES && layout != PMS_LAYOUT_BITSLICED) return 0;
+    return window_stride(t, l, layout);
 }
 
 int pms_set_config(const pms_config* cfg) {
@@ -826,6 +842,7 @@ int pms_last_stats(pms_stats* out) {
             c.last.seq_visits = st.visits;
             c.last.window_compares = st.visits * static_cast<uint64_t>(c.dv_nw);
             c.last.batches = ctr.batches;
+            c.last.candidate_slots = ctr.batches * 64u * (c.dv_group ? 16u : 1u);
         }
         c.last_pending = false;
     }
@@ -833,12 +850,14 @@ int pms_last_stats(pms_stats* out) {
     return PMS_OK;
 }
 
-int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l,
+int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t layout,
                       uint32_t* dev_windows, uint32_t* dev_bad, void* stream) {
     g_last_error.clear();
     if (!dev_seqs || !dev_windows) return fail(PMS_ERR_INVALID, "NULL device pointer");
     if (n < 1 || n > PMS_MAX_N || l < 1 || l > PMS_MAX_L || t < l || t > PMS_MAX_T)
         return fail(PMS_ERR_INVALID, "size out of range");
+    if (layout != PMS_LAYOUT_PLANES && (layout != PMS_LAYOUT_BITSLICED || l < 2))
+        return fail(PMS_ERR_INVALID, "bad layout (BITSLICED needs l >= 2)");
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     Ctx& c = g_ctx;
     PMS_TRY(init_ctx(c));
@@ -850,9 +869,10 @@ int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l,
     PMS_TRY(c.hv_meta.ensure(bytes));
     PMS_TRY(c.dv_meta.ensure(bytes));
     pms_win_job* jobs = c.hv_meta.as<pms_win_job>();
-    const int32_t stride = window_stride(t, l);
+    const int32_t stride = window_stride(t, l, layout);
     for (int32_t r = 0; r < n; ++r)
-        jobs[r] = {static_cast<uint64_t>(r) * t, static_cast<uint64_t>(r) * stride, t, l, stride, 0};
+        jobs[r] = {static_cast<uint64_t>(r) * t, static_cast<uint64_t>(r) * stride, t, l, stride, 0,
+                   layout, 0};
     PMS_HIP(hipMemcpyAsync(c.dv_meta.p, c.hv_meta.p, bytes, hipMemcpyHostToDevice, s));
     PMS_HIP(hipEventRecord(c.dv_copied, s));
     c.dv_copy_live = true;
@@ -873,18 +893,21 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
     PMS_TRY(init_ctx(c));
     const pms_config r = resolve(cfg, c.cfg);
     if (!config_ok(r)) return fail(PMS_ERR_INVALID, "configuration field out of range");
+    const bool group = r.variant != PMS_VARIANT_LANE;
     uint32_t grid = 0, waves = 0, qw = 0;
-    PMS_TRY(launch_shape(c, r, max_n, &grid, &waves, &qw));
+    PMS_TRY(launch_shape(c, r, max_n, group, &grid, &waves, &qw));
     hipStream_t s = static_cast<hipStream_t>(stream);
     PMS_HIP(hipEventRecord(c.ev[0], s));
     PMS_HIP(hipEventRecord(c.ev[1], s));
-    PMS_HIP(pms::launch_search(dev_instances, dev_work, static_cast<uint32_t>(n_work), dev_state,
-                               dev_counters, qw, grid, waves, s));
+    PMS_HIP((group ? pms::launch_search_group : pms::launch_search)(
+        dev_instances, dev_work, static_cast<uint32_t>(n_work), dev_state, dev_counters, qw, grid,
+        waves, s));
     PMS_HIP(hipEventRecord(c.ev[2], s));
     c.last = pms_stats{};
     c.last.grid = grid;
     c.last.wg_waves = waves;
     c.last.chunk = r.chunk;
+    c.last.variant = group ? PMS_VARIANT_GROUP : PMS_VARIANT_LANE;
     c.last_pending = true;
     c.dv_counters = false;
     return PMS_OK;
@@ -906,7 +929,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     b.out_cap = {capacity > 0 ? capacity : 1};
     plan_batch(b, cfg);
     uint32_t grid = 0, waves = 0, qw = 0;
-    PMS_TRY(launch_shape(c, cfg, b.max_n, &grid, &waves, &qw));
+    PMS_TRY(launch_shape(c, cfg, b.max_n, b.group, &grid, &waves, &qw));
     if (c.dv_copy_live) PMS_HIP(hipEventSynchronize(c.dv_copied));
     PMS_TRY(c.dv_win.ensure(std::max<size_t>(b.win_words * 4, 256)));
     PMS_TRY(c.dv_meta.ensure(b.meta_bytes));
@@ -919,7 +942,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     in->out = dev_out;
     in->out_cap = capacity;
     in->n = n;
-    in->nw_stride = window_stride(t, l);
+    in->nw_stride = window_stride(t, l, b.group ? PMS_LAYOUT_BITSLICED : PMS_LAYOUT_PLANES);
     in->l = l;
     in->d = d;
     reinterpret_cast<pms_dev_state*>(hm + b.off_state)->items_left = b.items_per_inst[0];
@@ -933,11 +956,11 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
                                 dev_seqs, c.dv_win.as<uint32_t>(),
                                 reinterpret_cast<uint32_t*>(dm + b.off_bad), s));
     PMS_HIP(hipEventRecord(c.ev[1], s));
-    PMS_HIP(pms::launch_search(reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
-                               reinterpret_cast<const pms_work_item*>(dm + b.off_work),
-                               static_cast<uint32_t>(b.work.size()),
-                               reinterpret_cast<pms_dev_state*>(dm + b.off_state),
-                               reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves, s));
+    PMS_HIP((b.group ? pms::launch_search_group : pms::launch_search)(
+        reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
+        reinterpret_cast<const pms_work_item*>(dm + b.off_work), static_cast<uint32_t>(b.work.size()),
+        reinterpret_cast<pms_dev_state*>(dm + b.off_state),
+        reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves, s));
     PMS_HIP(hipEventRecord(c.ev[2], s));
     PMS_HIP(hipMemcpyAsync(dev_count, dm + b.off_state + offsetof(pms_dev_state, count),
                            sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
@@ -945,8 +968,10 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     c.last.grid = grid;
     c.last.wg_waves = waves;
     c.last.chunk = cfg.chunk;
+    c.last.variant = b.group ? PMS_VARIANT_GROUP : PMS_VARIANT_LANE;
     c.last_pending = true;
     c.dv_counters = true;
+    c.dv_group = b.group;
     c.dv_state_off = b.off_state;
     c.dv_ctr_off = b.off_ctr;
     c.dv_nw = t - l + 1;
@@ -981,7 +1006,7 @@ int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_p
     for (uint32_t ch : chunks) {
         if (ch > total && ch != chunks[0]) continue;
         for (uint32_t w : waves) {
-            pms_config cfg{ch, w, 0, 8};
+            pms_config cfg{ch, w, 0, 8, c.cfg.variant};
             Batch b;
             b.shape = {Shape{n, t, l, d}};
             b.rows = {ptrs.data()};

@@ -19,6 +19,7 @@ typedef struct {
     uint64_t src_off;  // byte offset of the row in the packed input
     uint64_t dst_off;  // uint32 offset of the row's windows
     int32_t t, l, stride, inst;
+    int32_t layout, reserved;
 } pms_win_job;
 
 namespace pms {
@@ -35,13 +36,22 @@ hipError_t launch_fill(uint32_t* p, uint64_t words, uint32_t v, hipStream_t stre
 
 const void* search_kernel_symbol();
 
+hipError_t launch_search_group(const pms_dev_instance* insts, const pms_work_item* work,
+                               uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
+                               uint32_t q_words, uint32_t grid, uint32_t wg_waves,
+                               hipStream_t stream);
+
+const void* search_group_kernel_symbol();
+
 hipError_t valu_probe(int op, uint32_t blocks, uint32_t iters, uint32_t* sink, uint64_t* clocks,
                       hipStream_t s);
 
-// LDS words one wavefront of the search kernel needs for instances of up to
-// max_n sequences.
-inline uint32_t queue_words(int32_t max_n) {
-    return static_cast<uint32_t>(max_n > 1 ? max_n - 1 : 0) * PMS_QCAP;
+// LDS words of stage queues one wavefront needs for instances of up to
+// max_n sequences: LANE keeps one uint32 candidate per slot, GROUP a uint32
+// prefix and a uint16 alive mask.
+inline uint32_t queue_words(int32_t max_n, bool group) {
+    const uint32_t stages = static_cast<uint32_t>(max_n > 1 ? max_n - 1 : 0);
+    return stages * (group ? PMS_QCAP + PMS_QCAP / 2 : PMS_QCAP);
 }
 
 }  // namespace pms

@@ -38,31 +38,12 @@
 #include <stdint.h>
 
 #include "pms.h"
+#include "pms_device.h"
 #include "pms_internal.h"
 
 namespace {
 
-typedef __attribute__((address_space(4))) const uint32_t cu32;
-
-__device__ __forceinline__ uint32_t lane_id() {
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-
-// Number of set bits of m below the calling lane.
-__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
-                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
-}
-
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ uint64_t uni64(uint64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
-    return (static_cast<uint64_t>(hi) << 32) | lo;
-}
+using namespace pms_dev;
 
 // (x >> 16) | (x & 0xffff) in one instruction: the OR of the two bit planes
 // of an XOR difference marks every mismatching base position.
@@ -114,18 +95,6 @@ __device__ __forceinline__ uint32_t scan_sequence(cu32* W, uint32_t groups, uint
     return a0 < a1 ? a0 : a1;
 }
 
-// Reads a wave-uniform record of read-only data through the scalar cache.
-template <typename T>
-__device__ __forceinline__ T load_uniform(const T* p) {
-    static_assert(sizeof(T) % 4 == 0, "records are whole words");
-    cu32* w = (cu32*)(p);
-    T r;
-    uint32_t* rw = reinterpret_cast<uint32_t*>(&r);
-#pragma unroll
-    for (unsigned i = 0; i < sizeof(T) / 4; ++i) rw[i] = w[i];
-    return r;
-}
-
 }  // namespace
 
 // --------------------------------------------------------------------------
@@ -164,18 +133,37 @@ pms_windows_kernel(const pms_win_job* __restrict__ jobs, const uint8_t* __restri
     // a2: window j covers bases j .. j+l-1 (l <= 16, so at most two words).
     const int nw = t - l + 1;
     uint32_t* dst = windows + job.dst_off;
-    for (int j = threadIdx.x; j < stride; j += blockDim.x) {
-        const int jj = j < nw ? j : 0;
-        const int wq = jj >> 4, sh = 2 * (jj & 15);
-        const uint64_t two = (static_cast<uint64_t>(packed[wq + 1]) << 32) | packed[wq];
-        const uint32_t bits = static_cast<uint32_t>(two >> sh);
-        uint32_t hi = 0, lo = 0;
-        for (int p = 0; p < l; ++p) {
-            const uint32_t b = (bits >> (2 * p)) & 3u;
-            hi |= (b >> 1) << (l - 1 - p);
-            lo |= (b & 1u) << (l - 1 - p);
+    if (job.layout == PMS_LAYOUT_PLANES) {
+        for (int j = threadIdx.x; j < stride; j += blockDim.x) {
+            const int jj = j < nw ? j : 0;
+            const int wq = jj >> 4, sh = 2 * (jj & 15);
+            const uint64_t two = (static_cast<uint64_t>(packed[wq + 1]) << 32) | packed[wq];
+            const uint32_t bits = static_cast<uint32_t>(two >> sh);
+            uint32_t hi = 0, lo = 0;
+            for (int p = 0; p < l; ++p) {
+                const uint32_t b = (bits >> (2 * p)) & 3u;
+                hi |= (b >> 1) << (l - 1 - p);
+                lo |= (b & 1u) << (l - 1 - p);
+            }
+            dst[j] = (hi << 16) | lo;
         }
-        dst[j] = (hi << 16) | lo;
+    } else {
+        // Bit-sliced: word (g, p) bit j is the high bit of base p of window
+        // 32g+j, word (g, l+p) the low bit; windows past nw repeat window 0.
+        const int words = stride;  // groups * 2l
+        for (int q = threadIdx.x; q < words; q += blockDim.x) {
+            const int g = q / (2 * l), r = q % (2 * l);
+            const int p = r < l ? r : r - l;
+            const int plane = r < l ? 1 : 0;
+            uint32_t v = 0;
+            for (int j = 0; j < 32; ++j) {
+                const int w = 32 * g + j;
+                const int pos = (w < nw ? w : 0) + p;
+                const uint32_t b = (packed[pos >> 4] >> (2 * (pos & 15))) & 3u;
+                v |= ((b >> plane) & 1u) << j;
+            }
+            dst[q] = v;
+        }
     }
 }
 

@@ -43,9 +43,14 @@ class Result(ctypes.Structure):
                 ("count", ctypes.c_uint64), ("latency_ms", ctypes.c_double)]
 
 
+VARIANT_AUTO, VARIANT_LANE, VARIANT_GROUP = 0, 1, 2
+LAYOUT_PLANES, LAYOUT_BITSLICED = 0, 1
+
+
 class Config(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32), ("wg_waves", ctypes.c_uint32),
-                ("wgs_per_cu", ctypes.c_uint32), ("tail_split", ctypes.c_uint32)]
+                ("wgs_per_cu", ctypes.c_uint32), ("tail_split", ctypes.c_uint32),
+                ("variant", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -54,9 +59,10 @@ class Config(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("windows_ms", ctypes.c_double),
                 ("seq_visits", ctypes.c_uint64), ("batches", ctypes.c_uint64),
-                ("window_compares", ctypes.c_uint64), ("grid", ctypes.c_uint32),
-                ("wg_waves", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("reruns", ctypes.c_uint32)]
+                ("window_compares", ctypes.c_uint64), ("candidate_slots", ctypes.c_uint64),
+                ("grid", ctypes.c_uint32), ("wg_waves", ctypes.c_uint32),
+                ("chunk", ctypes.c_uint32), ("reruns", ctypes.c_uint32),
+                ("variant", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))
@@ -116,8 +122,8 @@ def _load():
         "pms_get_config": ([P(Config)], ctypes.c_int),
         "pms_autotune": ([i32, i32, i32, i32, ctypes.c_char_p, P(Config)], ctypes.c_int),
         "pms_last_stats": ([P(Stats)], ctypes.c_int),
-        "pms_window_stride": ([i32, i32], i32),
-        "pms_build_windows": ([vp, i32, i32, i32, vp, vp, vp], ctypes.c_int),
+        "pms_window_stride": ([i32, i32, i32], i32),
+        "pms_build_windows": ([vp, i32, i32, i32, i32, vp, vp, vp], ctypes.c_int),
         "pms_step_launch": ([vp, i32, i32, vp, i32, vp, vp, P(Config), vp], ctypes.c_int),
         "pms_solve_dev": ([vp, i32, i32, i32, i32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
         "pms_valu_probe": ([ctypes.c_int, i32, i32, P(ProbeResult)], ctypes.c_int),
@@ -215,10 +221,10 @@ def decode(code: int, l: int) -> str:
     return buf.raw[:l].decode()
 
 
-def set_config(chunk=0, wg_waves=0, wgs_per_cu=0, tail_split=8, reset=False):
+def set_config(chunk=0, wg_waves=0, wgs_per_cu=0, tail_split=8, variant=0, reset=False):
     if reset:
         return _check(_lib.pms_set_config(None))
-    cfg = Config(chunk, wg_waves, wgs_per_cu, tail_split)
+    cfg = Config(chunk, wg_waves, wgs_per_cu, tail_split, variant)
     return _check(_lib.pms_set_config(ctypes.byref(cfg)))
 
 
@@ -248,8 +254,8 @@ def valu_probe(op: str, waves_per_simd: int = 0, iters: int = 0) -> dict:
     return {k: float(getattr(r, k)) for k, _ in r._fields_ if k != "reserved"}
 
 
-def window_stride(t: int, l: int) -> int:
-    return int(_lib.pms_window_stride(t, l))
+def window_stride(t: int, l: int, layout: int = LAYOUT_BITSLICED) -> int:
+    return int(_lib.pms_window_stride(t, l, layout))
 
 
 # ---------------------------------------------------------------------------
@@ -262,9 +268,10 @@ def _stream_handle(stream) -> Optional[int]:
     return int(stream.cuda_stream)
 
 
-def build_windows(dev_seqs, n: int, t: int, l: int, dev_windows, dev_bad=None, stream=None):
+def build_windows(dev_seqs, n: int, t: int, l: int, dev_windows, dev_bad=None, stream=None,
+                  layout: int = LAYOUT_BITSLICED):
     return _check(_lib.pms_build_windows(
-        dev_seqs.data_ptr(), n, t, l, dev_windows.data_ptr(),
+        dev_seqs.data_ptr(), n, t, l, layout, dev_windows.data_ptr(),
         dev_bad.data_ptr() if dev_bad is not None else None, _stream_handle(stream)))
 
 

@@ -76,7 +76,7 @@ class _Req:
         self.future = future
         self.slot = -1
         self.dev_seqs = self.dev_win = self.dev_out = None
-        self.stride = nat.window_stride(self.t, l)
+        self.stride = nat.window_stride(self.t, l, nat.LAYOUT_BITSLICED) if l >= 2 else 0
         est_m, ev = _estimate(l, d, self.n, self.t)
         self.cap = int(min(4 ** l, 8 * est_m + 4096))
         self.cost_per_cand = (self.t - l + 1) * ev
@@ -123,7 +123,9 @@ class Server:
         self.items_per_step = int(items_per_step)
         self.copy_stream = torch.cuda.Stream(self.dev)
         self.max_inflight = int(max_inflight)
-        self.config = config
+        # Steps run the grouped kernel, whose windows are bit-sliced.
+        self.config = dict(config or {})
+        self.config["variant"] = nat.VARIANT_GROUP
         self.reserve = reserve  # fixed first output reservation (tests of the rerun path)
         self.d_insts = torch.zeros(MAX_SLOTS * 40, dtype=torch.uint8, device=self.dev)
         self.d_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8, device=self.dev)
@@ -150,6 +152,17 @@ class Server:
             self._validate(m, l, d)
         except nat.PmsError as e:
             fut.set_exception(e)
+            return fut
+        if l == 1:
+            # Four candidates: answered directly by the host-level solve.
+            t0 = time.perf_counter()
+            try:
+                codes = nat.solve(m, 1, d)
+            except nat.PmsError as e:
+                fut.set_exception(e)
+                return fut
+            t1 = time.perf_counter()
+            fut.set_result(Result(codes, int(codes.size), t0, t0, t1, 0, 0, 0))
             return fut
         with self.cv:
             if not self.running:
@@ -211,7 +224,8 @@ class Server:
                 self.dev, non_blocking=True)
             req.dev_win = torch.empty(req.n * req.stride, dtype=torch.int32, device=self.dev)
             req.dev_out = torch.empty(max(req.cap, 1), dtype=torch.int32, device=self.dev)
-        nat.build_windows(req.dev_seqs, req.n, req.t, req.l, req.dev_win, None, stream=self.stream)
+        nat.build_windows(req.dev_seqs, req.n, req.t, req.l, req.dev_win, None, stream=self.stream,
+                          layout=nat.LAYOUT_BITSLICED)
         self._write_slot(req)
 
     def _write_slot(self, req: _Req):

@@ -36,9 +36,9 @@ def test_struct_layouts_match_header(tmp_path):
     fields = {
         "pms_instance": ["seqs", "n", "t", "l", "d", "out_motifs", "capacity"],
         "pms_result": ["status", "count", "latency_ms"],
-        "pms_config": ["chunk", "wg_waves", "wgs_per_cu", "tail_split"],
+        "pms_config": ["chunk", "wg_waves", "wgs_per_cu", "tail_split", "variant"],
         "pms_stats": ["kernel_ms", "windows_ms", "seq_visits", "batches", "window_compares",
-                      "grid", "wg_waves", "chunk", "reruns"],
+                      "candidate_slots", "grid", "wg_waves", "chunk", "reruns", "variant"],
         "pms_dev_instance": ["windows", "out", "out_cap", "n", "nw_stride", "l", "d"],
         "pms_work_item": ["begin", "len", "inst"],
         "pms_dev_state": ["count", "visits", "t_done", "items_left"],
@@ -74,13 +74,23 @@ def test_decode_status_and_stride():
     for s, txt in [(0, "ok"), (1, "invalid argument"), (2, "output capacity exceeded"),
                    (3, "out of memory"), (4, "device error"), (9, "unknown status")]:
         assert nat.status_string(s) == txt
-    assert nat.window_stride(600, 15) == 592
-    assert nat.window_stride(600, 11) == 592
-    assert nat.window_stride(16, 16) == 16
-    assert nat.window_stride(17, 16) == 16
-    assert nat.window_stride(32, 16) == 32
-    assert nat.window_stride(10, 11) == 0
-    assert nat.window_stride(10, 17) == 0
+    P, B = nat.LAYOUT_PLANES, nat.LAYOUT_BITSLICED
+    assert nat.window_stride(600, 15, P) == 592
+    assert nat.window_stride(600, 11, P) == 592
+    assert nat.window_stride(16, 16, P) == 16
+    assert nat.window_stride(17, 16, P) == 16
+    assert nat.window_stride(32, 16, P) == 32
+    assert nat.window_stride(10, 11, P) == 0
+    assert nat.window_stride(10, 17, P) == 0
+    # bit-sliced: 2l words per group of 32 windows
+    assert nat.window_stride(600, 15, B) == 19 * 30
+    assert nat.window_stride(600, 11, B) == 19 * 22
+    assert nat.window_stride(16, 16, B) == 32
+    assert nat.window_stride(47, 16, B) == 32
+    assert nat.window_stride(48, 16, B) == 64
+    assert nat.window_stride(5, 1, B) == 0
+    assert nat.window_stride(5, 2, B) == 4
+    assert nat.window_stride(600, 15, 2) == 0
 
 
 @pytest.mark.parametrize("n,t,l,d", [(0, 10, 4, 1), (65, 10, 4, 1), (3, 10, 0, 0), (3, 10, 17, 1),
@@ -144,7 +154,10 @@ def test_config_validation():
     nat.set_config(chunk=4096, wg_waves=2)
     assert nat.get_config()["chunk"] == 4096 and nat.get_config()["wg_waves"] == 2
     nat.set_config(reset=True)
-    assert nat.get_config() == {"chunk": 16384, "wg_waves": 4, "wgs_per_cu": 0, "tail_split": 8}
+    assert nat.get_config() == {"chunk": 16384, "wg_waves": 4, "wgs_per_cu": 0, "tail_split": 8,
+                                "variant": 0}
+    with pytest.raises(nat.PmsError):
+        nat.set_config(variant=3)
 
 
 def test_injected_failure_propagates(monkeypatch):

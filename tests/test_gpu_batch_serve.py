@@ -180,3 +180,5 @@ def test_serving_rejects_invalid_requests(nat):
             f.result(timeout=10)
         ok = srv.submit(fmgen.random_seqs(3, 40, 2), 5, 1).result(timeout=60)
         assert np.array_equal(ok.motifs, oracle.solve(fmgen.random_seqs(3, 40, 2), 5, 1))
+        one = srv.submit(fmgen.random_seqs(3, 40, 3), 1, 0).result(timeout=60)
+        assert np.array_equal(one.motifs, oracle.solve(fmgen.random_seqs(3, 40, 3), 1, 0))

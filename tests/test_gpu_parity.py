@@ -36,6 +36,15 @@ def gpu_solve(nat, seqs, l, d):
     return res, nat.last_stats()
 
 
+@pytest.fixture(params=["lane", "group"])
+def variant(request, nat):
+    """Runs a test once per search kernel variant."""
+    v = {"lane": nat.VARIANT_LANE, "group": nat.VARIANT_GROUP}[request.param]
+    nat.set_config(variant=v)
+    yield v
+    nat.set_config(reset=True)
+
+
 def records(cfg):
     path = os.path.join(GOLDEN, f"{cfg}.json")
     if not os.path.exists(path):
@@ -49,7 +58,7 @@ def announce(msg):
 
 
 @pytest.mark.parametrize("cfg", ["plain_8_1", "plain_11_3", "plain_15_4"])
-def test_plain_configs_match_golden(nat, cfg):
+def test_plain_configs_match_golden(nat, variant, cfg):
     for r in records(cfg):
         announce(f"{cfg} seed={r['seed']}")
         inst = fmgen.gen_fm(r["l"], r["d"], r["n"], r["t"], r["seed"])
@@ -59,6 +68,7 @@ def test_plain_configs_match_golden(nat, cfg):
         assert [nat.decode(int(k), r["l"]) for k in got] == r["motifs"]
         assert st["seq_visits"] == r["skip_visits"]
         assert st["window_compares"] == r["skip_visits"] * (r["t"] - r["l"] + 1)
+        assert st["variant"] == variant
 
 
 def test_plain_15_4_sampled_candidates(nat):
@@ -82,7 +92,7 @@ def test_plain_15_4_sampled_candidates(nat):
         assert oracle.is_motif(inst.seqs, 15, 4, int(k))
 
 
-def test_random_small_instances(nat):
+def test_random_small_instances(nat, variant):
     """l <= 8 over every d regime, ragged window counts, n up to 30."""
     rng = np.random.default_rng(2024)
     for case in range(60):
@@ -102,7 +112,7 @@ def test_random_small_instances(nat):
         assert st["seq_visits"] == visits
 
 
-def test_random_large_l_sampled(nat):
+def test_random_large_l_sampled(nat, variant):
     """l in [10, 16]: exact comparison on an oracle sub-range of candidates,
     soundness of every motif, and the planted consensus."""
     rng = np.random.default_rng(77)
@@ -128,7 +138,7 @@ def test_random_large_l_sampled(nat):
 @pytest.mark.parametrize("l,d,n,t", [(1, 0, 3, 5), (1, 1, 2, 1), (4, 0, 1, 4), (6, 2, 1, 6),
                                      (16, 0, 2, 16), (16, 2, 1, 16), (5, 5, 3, 9), (7, 7, 2, 7),
                                      (8, 1, 64, 60), (9, 2, 64, 17), (12, 3, 3, 12)])
-def test_edge_shapes(nat, l, d, n, t):
+def test_edge_shapes(nat, variant, l, d, n, t):
     announce(f"edge l={l} d={d} n={n} t={t}")
     seqs = fmgen.random_seqs(n, t, 1000 * l + 10 * d + n)
     got, _ = gpu_solve(nat, seqs, l, d)
@@ -143,9 +153,9 @@ def test_edge_shapes(nat, l, d, n, t):
         assert oracle.is_motif(seqs, l, d, int(k))
 
 
-def test_window_count_ragged_tail(nat):
-    """Window counts around the 16-window scan groups: nw = 1..40."""
-    for nw in range(1, 41):
+def test_window_count_ragged_tail(nat, variant):
+    """Window counts around the 16- and 32-window scan groups: nw = 1..70."""
+    for nw in range(1, 71):
         l, d, n = 7, 1, 4
         t = l + nw - 1
         seqs = fmgen.random_seqs(n, t, 500 + nw)
@@ -194,14 +204,16 @@ def test_launch_configurations_agree(nat):
     inst = fmgen.gen_fm(11, 3, 20, 600, 0)
     want = oracle.solve(inst.seqs, 11, 3, mode="skip", return_visits=True)
     try:
-        for chunk in (64, 1024, 16384, 1 << 16):
-            for waves in (1, 2, 4, 8, 16):
-                for tail in (0, 8, 64):
-                    announce(f"config chunk={chunk} waves={waves} tail={tail}")
-                    nat.set_config(chunk=chunk, wg_waves=waves, tail_split=tail)
-                    got, st = gpu_solve(nat, inst.seqs, 11, 3)
-                    assert np.array_equal(got, want[0])
-                    assert st["seq_visits"] == want[1]
+        for var in (nat.VARIANT_LANE, nat.VARIANT_GROUP):
+            for chunk in (64, 1024, 16384, 1 << 16):
+                for waves in (1, 2, 4, 8, 16):
+                    for tail in (0, 8, 64):
+                        announce(f"config variant={var} chunk={chunk} waves={waves} tail={tail}")
+                        nat.set_config(chunk=chunk, wg_waves=waves, tail_split=tail, variant=var)
+                        got, st = gpu_solve(nat, inst.seqs, 11, 3)
+                        assert np.array_equal(got, want[0])
+                        assert st["seq_visits"] == want[1]
+                        assert st["variant"] == var
     finally:
         nat.set_config(reset=True)
 
@@ -224,31 +236,59 @@ def test_solve_dev_through_torch(nat):
     assert st["seq_visits"] == visits and st["kernel_ms"] > 0
 
 
-def test_build_windows_layout(nat):
-    """Bit-plane windows written by the device equal the documented layout."""
+def _reference_windows(seqs, l, layout):
+    """The documented window-table layouts, written out in Python."""
+    codes = {ord("A"): 0, ord("C"): 1, ord("G"): 2, ord("T"): 3}
+    n, t = seqs.shape
+    nw = t - l + 1
+    rows = []
+    for i in range(n):
+        base = [codes[int(x)] for x in seqs[i]]
+        if layout == 0:
+            stride = (nw + 15) // 16 * 16
+            row = []
+            for j in range(stride):
+                jj = j if j < nw else 0
+                hi = lo = 0
+                for p in range(l):
+                    b = base[jj + p]
+                    hi |= (b >> 1) << (l - 1 - p)
+                    lo |= (b & 1) << (l - 1 - p)
+                row.append((hi << 16) | lo)
+        else:
+            groups = (nw + 31) // 32
+            row = []
+            for g in range(groups):
+                words = [0] * (2 * l)
+                for j in range(32):
+                    w = 32 * g + j
+                    w = w if w < nw else 0
+                    for p in range(l):
+                        b = base[w + p]
+                        words[p] |= (b >> 1) << j
+                        words[l + p] |= (b & 1) << j
+                row.extend(words)
+        rows.append(row)
+    return np.array(rows, dtype=np.uint64).astype(np.uint32)
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_build_windows_layout(nat, layout):
+    """Windows written by the device equal the documented layouts."""
     import torch
-    seqs = fmgen.random_seqs(3, 37, 5)
+    seqs = fmgen.random_seqs(3, 77, 5)
     l = 9
-    stride = nat.window_stride(37, l)
+    stride = nat.window_stride(77, l, layout)
     dev = torch.from_numpy(seqs.reshape(-1).copy()).cuda()
     win = torch.zeros(3 * stride, dtype=torch.int32, device="cuda")
     bad = torch.zeros(1, dtype=torch.int32, device="cuda")
-    nat.build_windows(dev, 3, 37, l, win, bad)
+    nat.build_windows(dev, 3, 77, l, win, bad, layout=layout)
     torch.cuda.synchronize()
     got = win.cpu().numpy().view(np.uint32).reshape(3, stride)
-    codes = {ord("A"): 0, ord("C"): 1, ord("G"): 2, ord("T"): 3}
-    for i in range(3):
-        for j in range(stride):
-            jj = j if j < 37 - l + 1 else 0
-            hi = lo = 0
-            for p in range(l):
-                b = codes[int(seqs[i, jj + p])]
-                hi |= (b >> 1) << (l - 1 - p)
-                lo |= (b & 1) << (l - 1 - p)
-            assert got[i, j] == (hi << 16) | lo
+    assert np.array_equal(got, _reference_windows(seqs, l, layout))
     assert int(bad.item()) == 0
     seqs[1, 4] = ord("N")
     dev = torch.from_numpy(seqs.reshape(-1).copy()).cuda()
-    nat.build_windows(dev, 3, 37, l, win, bad)
+    nat.build_windows(dev, 3, 77, l, win, bad, layout=layout)
     torch.cuda.synchronize()
     assert int(bad.item()) == 1
