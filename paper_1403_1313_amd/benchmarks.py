@@ -58,6 +58,11 @@ def bench_batched(args):
         graph_ms.append(s["kernel_ms"])
         lat.extend(r.latency_ms for r in results)
     stats = nat.last_stats()
+    # One eager launch to split the search kernel from copies and windows.
+    os.environ["PMS_NO_GRAPH"] = "1"
+    nat.solve_many(work, caps)
+    eager = nat.last_stats()
+    del os.environ["PMS_NO_GRAPH"]
 
     parity = None
     gold = _golden("batched")
@@ -102,6 +107,10 @@ def bench_batched(args):
         "candidates_per_s": cands / wall,
         "window_compares_per_s": stats["window_compares"] / wall,
         "graph_ms_median": float(np.median(graph_ms)),
+        "eager": {"search_kernel_ms": eager["kernel_ms"], "windows_kernel_ms": eager["windows_ms"],
+                  "variant": eager["variant"], "grid": eager["grid"], "wg_waves": eager["wg_waves"],
+                  "slot_efficiency": eager["seq_visits"] / max(1, eager["candidate_slots"]),
+                  "window_compares_per_s_kernel": eager["window_compares"] / (eager["kernel_ms"] * 1e-3)},
         "instance_latency_ms_p50": _pct(lat, 50),
         "instance_latency_ms_p99": _pct(lat, 99),
         "total_motifs": int(sum(m.size for m in motifs)),

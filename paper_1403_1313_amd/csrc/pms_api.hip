@@ -262,6 +262,9 @@ struct Ctx {
 
 Ctx g_ctx;
 
+// About 32 work items per wavefront the device can hold resident.
+uint64_t target_items(const Ctx& c) { return static_cast<uint64_t>(std::max(c.cus, 1)) * 16u * 32u; }
+
 int init_ctx(Ctx& c) {
     if (c.ready) return PMS_OK;
     int count = 0;
@@ -307,21 +310,30 @@ int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, bool group, uint3
 }
 
 // Cuts each instance's candidate range into work items.  Instances go in
-// descending order of estimated work (longest first); inside an instance the
-// last tail_split/64 of the range uses items a quarter of `chunk`, so the
-// launch ends with small items.
-void build_work(Batch& b, const std::vector<int>& order, const pms_config& cfg) {
+// descending order of estimated work (longest first).  An instance receives a
+// number of items in proportion to its share of the launch's estimated work,
+// about `target_items` in all, and never items smaller than `chunk`
+// candidates; inside an instance the last tail_split/64 of the range uses
+// items a quarter of that size, so the launch ends with small items.
+void build_work(Batch& b, const std::vector<int>& order, const std::vector<double>& cost,
+                const pms_config& cfg, uint64_t target_items) {
     b.work.clear();
     b.items_per_inst.assign(b.shape.size(), 0);
+    double total_cost = 0;
+    for (int i : order) total_cost += cost[i];
     for (int i : order) {
         const Shape& s = b.shape[i];
         const uint64_t total = 1ull << (2 * s.l);
+        const double share = total_cost > 0 ? cost[i] / total_cost : 1.0;
+        const uint64_t want_items = std::max<uint64_t>(1, static_cast<uint64_t>(share * target_items));
+        uint64_t size = std::max<uint64_t>(cfg.chunk, (total + want_items - 1) / want_items);
+        size = std::min<uint64_t>(align_up(size, 64), 1ull << 30);
         const uint64_t tail = total * cfg.tail_split / 64;
         const uint64_t head_end = total - tail;
-        const uint64_t small = std::max<uint64_t>(64, cfg.chunk / 4);
+        const uint64_t small = std::max<uint64_t>(64, align_up(size / 4, 64));
         uint64_t k = 0;
         while (k < total) {
-            const uint64_t step = k < head_end ? cfg.chunk : small;
+            const uint64_t step = k < head_end ? size : small;
             const uint64_t len = std::min<uint64_t>(step, total - k);
             b.work.push_back({k, static_cast<uint32_t>(len), static_cast<uint32_t>(i)});
             b.items_per_inst[i]++;
@@ -331,7 +343,8 @@ void build_work(Batch& b, const std::vector<int>& order, const pms_config& cfg) 
 }
 
 // Lays out raw bytes, windows, outputs and the meta block for the instances.
-void plan_batch(Batch& b, const pms_config& cfg) {
+// target_items: about how many work items the launch should have in all.
+void plan_batch(Batch& b, const pms_config& cfg, uint64_t target_items) {
     const size_t m = b.shape.size();
     b.raw_off.resize(m);
     b.win_off.resize(m);
@@ -367,7 +380,7 @@ void plan_batch(Batch& b, const pms_config& cfg) {
     std::vector<int> order(m);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
-    build_work(b, order, cfg);
+    build_work(b, order, cost, cfg, target_items);
     size_t off = 0;
     b.off_insts = off;
     off = align_up(off + m * sizeof(pms_dev_instance), 256);
@@ -520,7 +533,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     b.shape = shapes;
     b.rows = rows;
     b.out_cap.assign(m, 0);
-    plan_batch(b, cfg);
+    plan_batch(b, cfg, target_items(c));
     PMS_TRY(stage_batch(c, b));
     PMS_TRY(run_batch(c, b, cfg, use_graph));
     counts.assign(m, 0);
@@ -561,7 +574,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
         r.shape = {shapes[i]};
         r.rows = {rows[i]};
         r.out_cap = {counts[i]};
-        plan_batch(r, cfg);
+        plan_batch(r, cfg, target_items(c));
         PMS_TRY(stage_batch(c, r));
         PMS_TRY(run_batch(c, r, cfg, false));
         const pms_dev_state* rs = c.h_back.as<pms_dev_state>(r.off_state);
@@ -927,7 +940,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     Batch b;
     b.shape = {Shape{n, t, l, d}};
     b.out_cap = {capacity > 0 ? capacity : 1};
-    plan_batch(b, cfg);
+    plan_batch(b, cfg, target_items(c));
     uint32_t grid = 0, waves = 0, qw = 0;
     PMS_TRY(launch_shape(c, cfg, b.max_n, b.group, &grid, &waves, &qw));
     if (c.dv_copy_live) PMS_HIP(hipEventSynchronize(c.dv_copied));
@@ -1011,7 +1024,7 @@ int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_p
             b.shape = {Shape{n, t, l, d}};
             b.rows = {ptrs.data()};
             b.out_cap = {0};
-            plan_batch(b, cfg);
+            plan_batch(b, cfg, target_items(c));
             PMS_TRY(stage_batch(c, b));
             double ms = 1e300;
             for (int rep = 0; rep < 3; ++rep) {

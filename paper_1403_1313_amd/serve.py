@@ -110,7 +110,7 @@ class Server:
     """Continuous-batching server.  ``submit`` returns a Future of ``Result``."""
 
     def __init__(self, mem_budget: int = 256 << 20, step_ms: float = 3.0,
-                 max_inflight: int = 2, compares_per_s: float = 1.1e13,
+                 max_inflight: int = 2, compares_per_s: float = 7e13,
                  device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
                  items_per_step: int = 8192):
         import torch
