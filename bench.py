@@ -31,7 +31,8 @@ VALU_INT32_PEAK = CUS * LANES_PER_CU * CLOCK_HZ          # lane-ops/s
 # (v_xor_b32, v_or_b32_sdwa, v_bcnt_u32_b32 and half of a v_min3_u32).
 LANE_OPS_PER_COMPARE = 3.5
 KERNELS = {1: ("pms_search_kernel", "pms_kernels.hip"),
-           2: ("pms_search_group_kernel", "pms_group.hip")}
+           2: ("pms_search_group_kernel", "pms_group.hip"),
+           3: ("pms_search_group64_kernel", "pms_group.hip")}
 
 
 def parse():
@@ -46,7 +47,7 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--config", default="plain_15_4", choices=["plain_8_1", "plain_11_3", "plain_15_4"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--variant", default="auto", choices=["auto", "lane", "group"],
+    ap.add_argument("--variant", default="auto", choices=["auto", "lane", "group16", "group64"],
                     help="search kernel variant")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle CPU-baseline sample")
@@ -98,7 +99,7 @@ def bench_plain(args):
     import fmgen
     from paper_1403_1313_amd import native as nat
 
-    nat.set_config(variant={"auto": 0, "lane": 1, "group": 2}[args.variant])
+    nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant])
     shape = fmgen.PLAIN[args.config]
     inst = fmgen.gen_fm(seed=args.seed, **shape)
     l, d, n, t = inst.l, inst.d, inst.n, inst.t
@@ -184,7 +185,7 @@ def bench_plain(args):
         "window_compares": wc,
         "candidate_slots": st["candidate_slots"],
         "slot_efficiency": st["seq_visits"] / max(1, st["candidate_slots"]),
-        "variant": {1: "lane", 2: "group"}[st["variant"]],
+        "variant": nat.VARIANT_NAMES[st["variant"]],
         "motifs": int(codes.size),
         "parity_vs_golden": parity,
         "launch": {"grid": st["grid"], "wg_waves": st["wg_waves"], "chunk": st["chunk"]},

@@ -113,11 +113,14 @@ const char* pms_last_error(void);
 
 /* Search kernel variants (pms_config.variant). */
 enum pms_variant {
-    PMS_VARIANT_AUTO = 0,  /* GROUP when every instance of a launch has l >= 2, else LANE */
-    PMS_VARIANT_LANE = 1,  /* one candidate per lane; per window v_xor + v_or_b32_sdwa +
-                              v_bcnt + v_min3 (bit-plane window layout) */
-    PMS_VARIANT_GROUP = 2  /* 16 candidates sharing l-2 bases per lane; 32 windows per
-                              register, carry-save counts (bit-sliced window layout) */
+    PMS_VARIANT_AUTO = 0,   /* GROUP64 when every instance of a launch has l >= 3, else GROUP
+                               when every instance has l >= 2, else LANE */
+    PMS_VARIANT_LANE = 1,   /* one candidate per lane; per window v_xor + v_or_b32_sdwa +
+                               v_bcnt + v_min3 (bit-plane window layout) */
+    PMS_VARIANT_GROUP = 2,  /* 16 candidates sharing l-2 bases per lane; 32 windows per
+                               register, carry-save counts (bit-sliced layout); l >= 2 */
+    PMS_VARIANT_GROUP64 = 3 /* 64 candidates sharing l-3 bases per lane (bit-sliced
+                               layout); l >= 3 */
 };
 
 /* Window table layouts (pms_build_windows). */
@@ -163,13 +166,13 @@ typedef struct {
                                 algorithmic window-compare count */
     uint64_t batches;        /* wavefront sequence scans executed */
     uint64_t window_compares;/* sum over instances of seq_visits x (t-l+1) */
-    uint64_t candidate_slots;/* candidate scan slots executed: batches x 64 (LANE) or
-                                batches x 64 x 16 (GROUP) */
+    uint64_t candidate_slots;/* candidate scan slots executed: batches x 64 x (1, 16 or 64
+                                candidates per lane) */
     uint32_t grid;           /* workgroups launched */
     uint32_t wg_waves;
     uint32_t chunk;
     uint32_t reruns;         /* relaunches caused by device output overflow */
-    uint32_t variant;        /* pms_variant actually launched (LANE or GROUP) */
+    uint32_t variant;        /* pms_variant actually launched (LANE, GROUP or GROUP64) */
     uint32_t reserved;
 } pms_stats;
 
@@ -244,8 +247,8 @@ typedef struct {
 
 /* One work item: candidates [begin, begin+len) of instance `inst`.  LANE
  * numbers candidates in bit-plane order (candidate k has high plane k >> l and
- * low plane k & (2^l - 1)); GROUP in dictionary order (k is the motif code),
- * and there begin and len must be multiples of 16.  Either way the items of
+ * low plane k & (2^l - 1)); GROUP and GROUP64 in dictionary order (k is the
+ * motif code), and there begin and len must be multiples of 16 and 64.  Either way the items of
  * an instance must cover [0, 4^l) once.  len is at most 2^31. */
 typedef struct {
     uint64_t begin;
@@ -276,7 +279,7 @@ typedef struct {
  * work items dev_work[0 .. n_work).  Each instance's survivors are appended
  * (unsorted, as motif codes) to its `out`; its state counts them.  cfg may be
  * NULL (current configuration); its variant selects the kernel and so the
- * window layout the instances must have (AUTO means GROUP here).
+ * window layout the instances must have (AUTO means GROUP64 here).
  * n_inst/n_work are the table lengths; max_n is the largest n over the
  * instances the items reference (it sizes LDS; an instance with more
  * sequences is refused and sets the counters' error flag).

@@ -121,7 +121,7 @@ pms_config default_config() {
 bool config_ok(const pms_config& c) {
     return c.chunk >= 64 && c.chunk % 64 == 0 && c.chunk <= (1u << 24) && c.wg_waves >= 1 &&
            c.wg_waves <= 16 && c.wgs_per_cu <= 64 && c.tail_split <= 64 &&
-           c.variant <= PMS_VARIANT_GROUP;
+           c.variant <= PMS_VARIANT_GROUP64;
 }
 
 pms_config resolve(const pms_config* c, const pms_config& cur) {
@@ -224,7 +224,7 @@ struct Batch {
     std::vector<uint32_t> items_per_inst;
     size_t raw_bytes = 0, win_words = 0, out_words = 0;
     int32_t max_n = 1, max_t = 1;
-    bool group = false;  // GROUP variant (bit-sliced layout) for this launch
+    uint32_t variant = PMS_VARIANT_LANE;  // kernel variant chosen for this launch
     // meta layout (bytes) inside d_meta / h_meta
     size_t off_insts = 0, off_jobs = 0, off_work = 0, off_state = 0, off_ctr = 0, off_bad = 0,
            meta_bytes = 0;
@@ -257,7 +257,7 @@ struct Ctx {
     size_t dv_state_off = 0, dv_ctr_off = 0;
     int32_t dv_nw = 0;
     bool dv_counters = false;
-    bool dv_group = false;
+    uint32_t dv_variant = PMS_VARIANT_LANE;
 };
 
 Ctx g_ctx;
@@ -290,16 +290,19 @@ int init_ctx(Ctx& c) {
 }
 
 // Workgroup shape and grid for a search launch.
-int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, bool group, uint32_t* grid,
+int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, uint32_t* grid,
                  uint32_t* waves, uint32_t* q_words) {
-    const uint32_t qw = pms::queue_words(max_n, group);
+    const uint32_t qw = pms::queue_words(max_n, variant);
     const size_t per_wave = static_cast<size_t>(qw + PMS_OUTBUF) * sizeof(uint32_t);
     uint32_t w = cfg.wg_waves;
+    if (variant == PMS_VARIANT_GROUP64) w = std::min<uint32_t>(w, PMS_GROUP64_MAX_THREADS / 64);
     while (w > 1 && per_wave * w > c.lds_per_block) --w;
     if (per_wave * w > c.lds_per_block)
         return fail(PMS_ERR_INVALID, "stage queues exceed the LDS of one workgroup");
     int per_cu = 0;
-    const void* fn = group ? pms::search_group_kernel_symbol() : pms::search_kernel_symbol();
+    const void* fn = variant == PMS_VARIANT_LANE
+                         ? pms::search_kernel_symbol()
+                         : pms::search_group_kernel_symbol(variant == PMS_VARIANT_GROUP64 ? 3 : 2);
     PMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * w, per_wave * w));
     if (per_cu < 1) per_cu = 1;
     if (cfg.wgs_per_cu > 0 && static_cast<int>(cfg.wgs_per_cu) < per_cu) per_cu = cfg.wgs_per_cu;
@@ -342,6 +345,17 @@ void build_work(Batch& b, const std::vector<int>& order, const std::vector<doubl
     }
 }
 
+// The kernel a launch uses: the requested variant when every instance allows
+// it (GROUP needs l >= 2, GROUP64 l >= 3), otherwise the next smaller one.
+uint32_t choose_variant(const std::vector<Shape>& shapes, uint32_t requested) {
+    int32_t min_l = PMS_MAX_L;
+    for (const Shape& s : shapes) min_l = std::min(min_l, s.l);
+    uint32_t v = requested == PMS_VARIANT_AUTO ? PMS_VARIANT_GROUP64 : requested;
+    if (v == PMS_VARIANT_GROUP64 && min_l < 3) v = PMS_VARIANT_GROUP;
+    if (v == PMS_VARIANT_GROUP && min_l < 2) v = PMS_VARIANT_LANE;
+    return v;
+}
+
 // Lays out raw bytes, windows, outputs and the meta block for the instances.
 // target_items: about how many work items the launch should have in all.
 void plan_batch(Batch& b, const pms_config& cfg, uint64_t target_items) {
@@ -354,10 +368,8 @@ void plan_batch(Batch& b, const pms_config& cfg, uint64_t target_items) {
     b.raw_bytes = b.win_words = b.out_words = 0;
     b.max_n = 1;
     b.max_t = 1;
-    b.group = cfg.variant != PMS_VARIANT_LANE;
-    for (size_t i = 0; i < m; ++i)
-        if (b.shape[i].l < 2) b.group = false;
-    const int32_t layout = b.group ? PMS_LAYOUT_BITSLICED : PMS_LAYOUT_PLANES;
+    b.variant = choose_variant(b.shape, cfg.variant);
+    const int32_t layout = b.variant == PMS_VARIANT_LANE ? PMS_LAYOUT_PLANES : PMS_LAYOUT_BITSLICED;
     std::vector<double> cost(m);
     for (size_t i = 0; i < m; ++i) {
         const Shape& s = b.shape[i];
@@ -421,7 +433,8 @@ int stage_batch(Ctx& c, Batch& b) {
         insts[i].out = c.d_out.as<uint32_t>() + b.out_off[i];
         insts[i].out_cap = b.out_cap[i];
         insts[i].n = s.n;
-        insts[i].nw_stride = window_stride(s.t, s.l, b.group ? PMS_LAYOUT_BITSLICED : PMS_LAYOUT_PLANES);
+        insts[i].nw_stride = window_stride(
+            s.t, s.l, b.variant == PMS_VARIANT_LANE ? PMS_LAYOUT_PLANES : PMS_LAYOUT_BITSLICED);
         insts[i].l = s.l;
         insts[i].d = s.d;
         state[i].items_left = b.items_per_inst[i];
@@ -429,6 +442,16 @@ int stage_batch(Ctx& c, Batch& b) {
     memcpy(c.h_meta.as<char>(b.off_jobs), b.jobs.data(), b.jobs.size() * sizeof(pms_win_job));
     memcpy(c.h_meta.as<char>(b.off_work), b.work.data(), b.work.size() * sizeof(pms_work_item));
     return PMS_OK;
+}
+
+hipError_t launch_variant(uint32_t variant, const pms_dev_instance* insts,
+                          const pms_work_item* work, uint32_t n_work, pms_dev_state* state,
+                          pms_dev_counters* ctr, uint32_t qw, uint32_t grid, uint32_t waves,
+                          hipStream_t s) {
+    if (variant == PMS_VARIANT_LANE)
+        return pms::launch_search(insts, work, n_work, state, ctr, qw, grid, waves, s);
+    return pms::launch_search_group(insts, work, n_work, state, ctr, qw, grid, waves, s,
+                                    variant == PMS_VARIANT_GROUP64 ? 3 : 2);
 }
 
 // Enqueues copy-in, both kernels and copy-back of the state block on c.stream.
@@ -443,11 +466,12 @@ int enqueue_batch(Ctx& c, const Batch& b, bool timed, uint32_t grid, uint32_t wa
                                 c.d_raw.as<uint8_t>(), c.d_win.as<uint32_t>(),
                                 reinterpret_cast<uint32_t*>(dm + b.off_bad), c.stream));
     if (timed) PMS_HIP(hipEventRecord(c.ev[1], c.stream));
-    PMS_HIP((b.group ? pms::launch_search_group : pms::launch_search)(
-        reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
-        reinterpret_cast<const pms_work_item*>(dm + b.off_work), static_cast<uint32_t>(b.work.size()),
-        reinterpret_cast<pms_dev_state*>(dm + b.off_state),
-        reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves, c.stream));
+    PMS_HIP(launch_variant(b.variant, reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
+                           reinterpret_cast<const pms_work_item*>(dm + b.off_work),
+                           static_cast<uint32_t>(b.work.size()),
+                           reinterpret_cast<pms_dev_state*>(dm + b.off_state),
+                           reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves,
+                           c.stream));
     if (timed) PMS_HIP(hipEventRecord(c.ev[2], c.stream));
     PMS_HIP(hipMemcpyAsync(c.h_back.as<char>(b.off_state), dm + b.off_state,
                            b.meta_bytes - b.off_state, hipMemcpyDeviceToHost, c.stream));
@@ -461,14 +485,14 @@ std::string graph_signature(const Ctx& c, const Batch& b, const pms_config& cfg)
       << b.meta_bytes << ':' << b.off_state << ':' << b.jobs.size() << ':' << b.work.size()
       << ':' << b.max_n << ':' << b.max_t << ':' << cfg.chunk << ':' << cfg.wg_waves << ':'
       << cfg.wgs_per_cu << ':' << b.shape.size() << ':' << b.off_insts << ':' << b.off_jobs << ':'
-      << b.off_work << ':' << b.off_ctr << ':' << b.off_bad << ':' << b.group;
+      << b.off_work << ':' << b.off_ctr << ':' << b.off_bad << ':' << b.variant;
     return o.str();
 }
 
 // Runs a staged batch: eagerly (timed with events) or through the graph.
 int run_batch(Ctx& c, Batch& b, const pms_config& cfg, bool use_graph) {
     uint32_t grid = 0, waves = 0, qw = 0;
-    PMS_TRY(launch_shape(c, cfg, b.max_n, b.group, &grid, &waves, &qw));
+    PMS_TRY(launch_shape(c, cfg, b.max_n, b.variant, &grid, &waves, &qw));
     if (use_graph) {
         const std::string sig = graph_signature(c, b, cfg);
         if (!c.gexec || sig != c.gsig) {
@@ -510,7 +534,7 @@ int run_batch(Ctx& c, Batch& b, const pms_config& cfg, bool use_graph) {
     c.last.grid = grid;
     c.last.wg_waves = waves;
     c.last.chunk = cfg.chunk;
-    c.last.variant = b.group ? PMS_VARIANT_GROUP : PMS_VARIANT_LANE;
+    c.last.variant = b.variant;
     c.last_pending = false;
     return PMS_OK;
 }
@@ -557,7 +581,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     c.last.seq_visits = visits;
     c.last.window_compares = wcmp;
     c.last.batches = ctr->batches;
-    c.last.candidate_slots = ctr->batches * 64u * (b.group ? 16u : 1u);
+    c.last.candidate_slots = ctr->batches * 64u * pms::candidates_per_lane(b.variant);
     c.last.reruns = 0;
     // Outputs larger than the device estimate: solve those again with the
     // exact capacity (the count is exact, so one rerun suffices).
@@ -855,7 +879,7 @@ int pms_last_stats(pms_stats* out) {
             c.last.seq_visits = st.visits;
             c.last.window_compares = st.visits * static_cast<uint64_t>(c.dv_nw);
             c.last.batches = ctr.batches;
-            c.last.candidate_slots = ctr.batches * 64u * (c.dv_group ? 16u : 1u);
+            c.last.candidate_slots = ctr.batches * 64u * pms::candidates_per_lane(c.dv_variant);
         }
         c.last_pending = false;
     }
@@ -906,21 +930,20 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
     PMS_TRY(init_ctx(c));
     const pms_config r = resolve(cfg, c.cfg);
     if (!config_ok(r)) return fail(PMS_ERR_INVALID, "configuration field out of range");
-    const bool group = r.variant != PMS_VARIANT_LANE;
+    const uint32_t variant = r.variant == PMS_VARIANT_AUTO ? PMS_VARIANT_GROUP64 : r.variant;
     uint32_t grid = 0, waves = 0, qw = 0;
-    PMS_TRY(launch_shape(c, r, max_n, group, &grid, &waves, &qw));
+    PMS_TRY(launch_shape(c, r, max_n, variant, &grid, &waves, &qw));
     hipStream_t s = static_cast<hipStream_t>(stream);
     PMS_HIP(hipEventRecord(c.ev[0], s));
     PMS_HIP(hipEventRecord(c.ev[1], s));
-    PMS_HIP((group ? pms::launch_search_group : pms::launch_search)(
-        dev_instances, dev_work, static_cast<uint32_t>(n_work), dev_state, dev_counters, qw, grid,
-        waves, s));
+    PMS_HIP(launch_variant(variant, dev_instances, dev_work, static_cast<uint32_t>(n_work), dev_state,
+                           dev_counters, qw, grid, waves, s));
     PMS_HIP(hipEventRecord(c.ev[2], s));
     c.last = pms_stats{};
     c.last.grid = grid;
     c.last.wg_waves = waves;
     c.last.chunk = r.chunk;
-    c.last.variant = group ? PMS_VARIANT_GROUP : PMS_VARIANT_LANE;
+    c.last.variant = variant;
     c.last_pending = true;
     c.dv_counters = false;
     return PMS_OK;
@@ -942,7 +965,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     b.out_cap = {capacity > 0 ? capacity : 1};
     plan_batch(b, cfg, target_items(c));
     uint32_t grid = 0, waves = 0, qw = 0;
-    PMS_TRY(launch_shape(c, cfg, b.max_n, b.group, &grid, &waves, &qw));
+    PMS_TRY(launch_shape(c, cfg, b.max_n, b.variant, &grid, &waves, &qw));
     if (c.dv_copy_live) PMS_HIP(hipEventSynchronize(c.dv_copied));
     PMS_TRY(c.dv_win.ensure(std::max<size_t>(b.win_words * 4, 256)));
     PMS_TRY(c.dv_meta.ensure(b.meta_bytes));
@@ -955,7 +978,8 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     in->out = dev_out;
     in->out_cap = capacity;
     in->n = n;
-    in->nw_stride = window_stride(t, l, b.group ? PMS_LAYOUT_BITSLICED : PMS_LAYOUT_PLANES);
+    in->nw_stride = window_stride(
+        t, l, b.variant == PMS_VARIANT_LANE ? PMS_LAYOUT_PLANES : PMS_LAYOUT_BITSLICED);
     in->l = l;
     in->d = d;
     reinterpret_cast<pms_dev_state*>(hm + b.off_state)->items_left = b.items_per_inst[0];
@@ -969,11 +993,11 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
                                 dev_seqs, c.dv_win.as<uint32_t>(),
                                 reinterpret_cast<uint32_t*>(dm + b.off_bad), s));
     PMS_HIP(hipEventRecord(c.ev[1], s));
-    PMS_HIP((b.group ? pms::launch_search_group : pms::launch_search)(
-        reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
-        reinterpret_cast<const pms_work_item*>(dm + b.off_work), static_cast<uint32_t>(b.work.size()),
-        reinterpret_cast<pms_dev_state*>(dm + b.off_state),
-        reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves, s));
+    PMS_HIP(launch_variant(b.variant, reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
+                           reinterpret_cast<const pms_work_item*>(dm + b.off_work),
+                           static_cast<uint32_t>(b.work.size()),
+                           reinterpret_cast<pms_dev_state*>(dm + b.off_state),
+                           reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves, s));
     PMS_HIP(hipEventRecord(c.ev[2], s));
     PMS_HIP(hipMemcpyAsync(dev_count, dm + b.off_state + offsetof(pms_dev_state, count),
                            sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
@@ -981,10 +1005,10 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     c.last.grid = grid;
     c.last.wg_waves = waves;
     c.last.chunk = cfg.chunk;
-    c.last.variant = b.group ? PMS_VARIANT_GROUP : PMS_VARIANT_LANE;
+    c.last.variant = b.variant;
     c.last_pending = true;
     c.dv_counters = true;
-    c.dv_group = b.group;
+    c.dv_variant = b.variant;
     c.dv_state_off = b.off_state;
     c.dv_ctr_off = b.off_ctr;
     c.dv_nw = t - l + 1;

@@ -98,13 +98,39 @@ __device__ __forceinline__ uint32_t count_le(uint32_t c1, uint32_t c2, uint32_t 
     return ~gt;
 }
 
-// One sequence scan for the lane's group: returns the 16-bit mask of
-// candidates with a window within d, restricted to `alive`.
-// W: the sequence's bit-sliced row (groups x 2L words), wave-uniform.
-template <int P>
-__device__ __forceinline__ uint32_t scan_group(cu32* W, uint32_t groups, uint32_t prefix,
-                                               int d, uint32_t alive) {
-    constexpr int L = P + 2;
+// A wave-uniform value copied into a VGPR.  VALU instructions that read an
+// SGPR issue at half rate on gfx950; the selection tree below reads these
+// copies instead, so it runs at full rate.
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
+    uint32_t r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+// Alive / pass masks: 16 candidates per group (S = 2) or 64 (S = 3).
+template <int S> struct MaskOf { typedef uint32_t type; };
+template <> struct MaskOf<3> { typedef uint64_t type; };
+
+// One sequence scan for the lane's group of 4^S candidates that share the
+// P = l - S prefix bases `prefix`: returns the mask of candidates with a
+// window within d, restricted to `alive`.  W: the sequence's bit-sliced row
+// (groups x 2l words), wave-uniform.
+//
+// Per 32 windows: the prefix count c (carry-save tree), thresholds
+// T_k = [c <= d - k] for k = 0..S, then a selection tree over the suffix
+// positions: with s_q[b] = mismatch of base b at suffix position q,
+//   U_1[b1][k]    = s_1[b1] ? T[k+1] : T[k]                 k = 0..S-1
+//   U_j[..bj][k]  = s_j[bj] ? U_{j-1}[..][k+1] : U_{j-1}[..][k]
+// U_j[..][k] = [c + s_1 + .. + s_j <= d - k].  The last level is folded into
+// the accumulators: a candidate has a good window where
+//   U_{S-1}[..][1]  |  (~s_S[bS] & U_{S-1}[..][0]).
+template <int P, int S>
+__device__ __forceinline__ typename MaskOf<S>::type scan_group(
+        cu32* W, uint32_t groups, uint32_t prefix, int d, typename MaskOf<S>::type alive) {
+    typedef typename MaskOf<S>::type Mask;
+    constexpr int L = P + S;
+    constexpr int K = 1 << (2 * S);    // candidates per group
+    constexpr int N1 = K / 4;          // nodes of the next-to-last level
     uint32_t ch[P > 0 ? P : 1], cl[P > 0 ? P : 1];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -112,78 +138,114 @@ __device__ __forceinline__ uint32_t scan_group(cu32* W, uint32_t groups, uint32_
         ch[p] = 0u - (b >> 1);
         cl[p] = 0u - (b & 1u);
     }
-    uint32_t found[16];
+    uint32_t found[K], top[N1];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) found[c] = 0u;
-    uint32_t found_all = 0u;
+    for (int c = 0; c < K; ++c) found[c] = 0u;
+#pragma unroll
+    for (int c = 0; c < N1; ++c) top[c] = 0u;
     for (uint32_t gi = 0; gi < groups; ++gi, W += 2 * L) {
         uint32_t m[P > 0 ? P : 1];
 #pragma unroll
         for (int p = 0; p < P; ++p) m[p] = (W[p] ^ ch[p]) | (W[L + p] ^ cl[p]);
         uint32_t c1 = 0, c2 = 0, c4 = 0, c8 = 0;
         if (P > 0) count_bits<P>(m, c1, c2, c4, c8);
-        const uint32_t t0 = count_le(c1, c2, c4, c8, d);
-        const uint32_t t1 = count_le(c1, c2, c4, c8, d - 1);
-        const uint32_t t2 = count_le(c1, c2, c4, c8, d - 2);
-        found_all |= t2;
-        // Mismatch of each base at the last two positions (wave-uniform):
-        // base 0 (A=00) mismatches where hi|lo, C=01 where hi|~lo, G=10 where
-        // ~hi|lo, T=11 where ~(hi&lo).
-        const uint32_t ha = W[P], la = W[L + P], hb = W[P + 1], lb = W[L + P + 1];
-        const uint32_t sa[4] = {ha | la, ha | ~la, ~ha | la, ~(ha & la)};
-        const uint32_t sb[4] = {hb | lb, hb | ~lb, ~hb | lb, ~(hb & lb)};
+        uint32_t t[S + 1];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const uint32_t nu = ~(sa[c >> 2] | sb[c & 3]);  // no suffix mismatch
-            const uint32_t nv = ~(sa[c >> 2] & sb[c & 3]);  // at most one
-            found[c] |= t1 & nv;
-            found[c] |= t0 & nu;
+        for (int k = 0; k <= S; ++k) t[k] = count_le(c1, c2, c4, c8, d - k);
+        // Suffix mismatch vectors (base 0 = A = 00 mismatches where hi|lo,
+        // C = 01 where hi|~lo, G = 10 where ~hi|lo, T = 11 where ~(hi&lo)),
+        // computed on the scalar unit and copied to VGPRs.
+        uint32_t sv[S][4];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const uint32_t h = W[P + q], lo = W[L + P + q];
+            sv[q][0] = to_vgpr(h | lo);
+            sv[q][1] = to_vgpr(h | ~lo);
+            sv[q][2] = to_vgpr(~h | lo);
+            sv[q][3] = to_vgpr(~(h & lo));
+        }
+        // Selection tree down to the next-to-last level.
+        uint32_t u[N1][S];            // level S-1, thresholds k = 0..1 used
+        if (S == 2) {
+#pragma unroll
+            for (int b1 = 0; b1 < 4; ++b1) {
+                const uint32_t sm = sv[0][b1];
+                u[b1][0] = (sm & t[1]) | (~sm & t[0]);
+                u[b1][1] = (sm & t[2]) | (~sm & t[1]);
+            }
+        } else {
+#pragma unroll
+            for (int b1 = 0; b1 < 4; ++b1) {
+                const uint32_t sm = sv[0][b1];
+                uint32_t v1[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) v1[k] = (sm & t[k + 1]) | (~sm & t[k]);
+#pragma unroll
+                for (int b2 = 0; b2 < 4; ++b2) {
+                    const uint32_t sn = sv[1][b2];
+                    u[b1 * 4 + b2][0] = (sn & v1[1]) | (~sn & v1[0]);
+                    u[b1 * 4 + b2][1] = (sn & v1[2]) | (~sn & v1[1]);
+                }
+            }
+        }
+#pragma unroll
+        for (int n = 0; n < N1; ++n) {
+            top[n] |= u[n][1];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) found[n * 4 + b] |= u[n][0] & ~sv[S - 1][b];
         }
     }
-    uint32_t pass = 0u;
+    Mask pass = 0;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) pass |= ((found[c] | found_all) != 0u ? 1u : 0u) << c;
+    for (int c = 0; c < K; ++c)
+        pass |= static_cast<Mask>((found[c] | top[c >> 2]) != 0u ? 1u : 0u) << c;
     return pass & alive;
 }
 
 // Dispatch on the number of prefix positions (wave-uniform).
-__device__ __forceinline__ uint32_t scan_group_any(uint32_t P, cu32* W, uint32_t groups,
-                                                   uint32_t prefix, int d, uint32_t alive) {
+template <int S>
+__device__ __forceinline__ typename MaskOf<S>::type scan_group_any(
+        uint32_t P, cu32* W, uint32_t groups, uint32_t prefix, int d,
+        typename MaskOf<S>::type alive) {
     switch (P) {
-        case 0: return scan_group<0>(W, groups, prefix, d, alive);
-        case 1: return scan_group<1>(W, groups, prefix, d, alive);
-        case 2: return scan_group<2>(W, groups, prefix, d, alive);
-        case 3: return scan_group<3>(W, groups, prefix, d, alive);
-        case 4: return scan_group<4>(W, groups, prefix, d, alive);
-        case 5: return scan_group<5>(W, groups, prefix, d, alive);
-        case 6: return scan_group<6>(W, groups, prefix, d, alive);
-        case 7: return scan_group<7>(W, groups, prefix, d, alive);
-        case 8: return scan_group<8>(W, groups, prefix, d, alive);
-        case 9: return scan_group<9>(W, groups, prefix, d, alive);
-        case 10: return scan_group<10>(W, groups, prefix, d, alive);
-        case 11: return scan_group<11>(W, groups, prefix, d, alive);
-        case 12: return scan_group<12>(W, groups, prefix, d, alive);
-        case 13: return scan_group<13>(W, groups, prefix, d, alive);
-        default: return scan_group<14>(W, groups, prefix, d, alive);
+        case 0: return scan_group<0, S>(W, groups, prefix, d, alive);
+        case 1: return scan_group<1, S>(W, groups, prefix, d, alive);
+        case 2: return scan_group<2, S>(W, groups, prefix, d, alive);
+        case 3: return scan_group<3, S>(W, groups, prefix, d, alive);
+        case 4: return scan_group<4, S>(W, groups, prefix, d, alive);
+        case 5: return scan_group<5, S>(W, groups, prefix, d, alive);
+        case 6: return scan_group<6, S>(W, groups, prefix, d, alive);
+        case 7: return scan_group<7, S>(W, groups, prefix, d, alive);
+        case 8: return scan_group<8, S>(W, groups, prefix, d, alive);
+        case 9: return scan_group<9, S>(W, groups, prefix, d, alive);
+        case 10: return scan_group<10, S>(W, groups, prefix, d, alive);
+        case 11: return scan_group<11, S>(W, groups, prefix, d, alive);
+        case 12: return scan_group<12, S>(W, groups, prefix, d, alive);
+        case 13: return scan_group<13, S>(W, groups, prefix, d, alive);
+        default: return scan_group<(S == 2 ? 14 : 13), S>(W, groups, prefix, d, alive);
     }
 }
 
-}  // namespace
-
-extern "C" __global__ void __launch_bounds__(1024)
-pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
-                        const pms_work_item* __restrict__ work, uint32_t n_work,
-                        pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
-                        uint32_t q_words) {
-    extern __shared__ uint32_t lds[];
+// Persistent grouped search; S = 2 (16 candidates per lane) or 3 (64).
+template <int S>
+__device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict__ insts,
+                                              const pms_work_item* __restrict__ work,
+                                              uint32_t n_work, pms_dev_state* __restrict__ state,
+                                              pms_dev_counters* __restrict__ ctr,
+                                              uint32_t q_words) {
+    typedef typename MaskOf<S>::type Mask;
+    constexpr int K = 1 << (2 * S);
     constexpr uint32_t kNone = 0xffffffffu;
+    constexpr Mask kAll = static_cast<Mask>(~static_cast<Mask>(0)) >> (8 * sizeof(Mask) - K);
+    extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
     const uint32_t wave = uni(threadIdx.x >> 6);
     // Per wavefront: queue prefixes [stages][QCAP] u32, queue masks
-    // [stages][QCAP] u16, survivor staging [OUTBUF] u32.
+    // [stages][QCAP] Mask, survivor staging [OUTBUF] u32.
     uint32_t* const qp = lds + wave * (q_words + PMS_OUTBUF);
-    const uint32_t stages_cap = q_words / (PMS_QCAP + PMS_QCAP / 2);
-    uint16_t* const qm = reinterpret_cast<uint16_t*>(qp + stages_cap * PMS_QCAP);
+    constexpr uint32_t kEntryWords = 1 + sizeof(Mask) / 4;
+    const uint32_t stages_cap = q_words / (kEntryWords * PMS_QCAP);
+    Mask* const qm = reinterpret_cast<Mask*>(qp + stages_cap * PMS_QCAP);
     uint32_t* const ob = qp + q_words;
 
     uint32_t cur = kNone, pending = 0, stash = kNone;
@@ -201,7 +263,8 @@ pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
     int d = 0;
 
     for (;;) {
-        uint32_t s, prefix = 0, alive = 0;
+        uint32_t s, prefix = 0;
+        Mask alive = 0;
         const uint64_t full = ballot(counts >= 64u);
         if (full) {
             s = 63u - static_cast<uint32_t>(__builtin_clzll(full));
@@ -214,7 +277,7 @@ pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
             s = 0;
             const uint64_t g = next + lane;
             prefix = static_cast<uint32_t>(g);
-            alive = g < end ? 0xffffu : 0u;
+            alive = g < end ? kAll : static_cast<Mask>(0);
             next += 64;
         } else {
             if (stash == kNone && more) {
@@ -228,8 +291,8 @@ pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
                     const pms_work_item wi = load_uniform(work + item);
                     if (wi.inst == cur) {
                         ++pending;
-                        next = wi.begin >> 4;
-                        end = (wi.begin + wi.len) >> 4;
+                        next = wi.begin >> (2 * S);
+                        end = (wi.begin + wi.len) >> (2 * S);
                     } else {
                         stash = item;
                     }
@@ -267,7 +330,7 @@ pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
                 const pms_work_item wi = load_uniform(work + stash);
                 const pms_dev_instance in = load_uniform(insts + wi.inst);
                 stash = kNone;
-                if (in.n < 1 || in.l < 2 || (static_cast<uint32_t>(in.n) - 1u) > stages_cap) {
+                if (in.n < 1 || in.l < S || (static_cast<uint32_t>(in.n) - 1u) > stages_cap) {
                     if (lane == 0) atomicOr(&ctr->error, 1u);
                     continue;
                 }
@@ -277,12 +340,12 @@ pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
                 cap = in.out_cap;
                 n = static_cast<uint32_t>(in.n);
                 row = static_cast<uint32_t>(in.nw_stride);
-                P = static_cast<uint32_t>(in.l) - 2u;
-                groups = row / (2u * (P + 2u));
+                P = static_cast<uint32_t>(in.l) - S;
+                groups = row / (2u * (P + S));
                 d = in.d;
                 pending = 1;
-                next = wi.begin >> 4;
-                end = (wi.begin + wi.len) >> 4;
+                next = wi.begin >> (2 * S);
+                end = (wi.begin + wi.len) >> (2 * S);
                 continue;
             }
             s = static_cast<uint32_t>(__builtin_ctzll(nz));
@@ -294,11 +357,11 @@ pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
             if (lane == s) counts = 0;
         }
 
-        // One sequence scan for 64 groups (up to 1024 candidates).
-        const uint32_t pass = scan_group_any(P, W + s * row, groups, prefix, d, alive);
-        visits += static_cast<uint32_t>(__builtin_popcount(alive));
+        // One sequence scan for 64 groups.
+        const Mask pass = scan_group_any<S>(P, W + s * row, groups, prefix, d, alive);
+        visits += static_cast<uint32_t>(__builtin_popcountll(static_cast<uint64_t>(alive)));
         ++batches;
-        const bool keep = pass != 0u;
+        const bool keep = pass != 0;
         const uint64_t pm = ballot(keep);
         if (pm) {
             if (s + 1 < n) {
@@ -306,16 +369,22 @@ pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
                 const uint32_t r = rank_below(pm);
                 if (keep) {
                     qp[s * PMS_QCAP + base + r] = prefix;
-                    qm[s * PMS_QCAP + base + r] = static_cast<uint16_t>(pass);
+                    qm[s * PMS_QCAP + base + r] = pass;
                 }
                 if (lane == s + 1) counts += static_cast<uint32_t>(__builtin_popcountll(pm));
             } else {
-                // Survivors: one code per alive candidate, compacted by ballot.
-                for (uint32_t c = 0; c < 16u; ++c) {
-                    const bool hit = (pass >> c) & 1u;
+                // Survivors: each lane writes its alive candidates in turn;
+                // every round compacts one code per lane by ballot.
+                Mask left = pass;
+                for (;;) {
+                    const bool hit = left != 0;
                     const uint64_t hm = ballot(hit);
-                    if (!hm) continue;
-                    if (hit) ob[nob + rank_below(hm)] = (prefix << 4) | c;
+                    if (!hm) break;
+                    if (hit) {
+                        const uint32_t c = static_cast<uint32_t>(__builtin_ctzll(static_cast<uint64_t>(left)));
+                        ob[nob + rank_below(hm)] = (prefix << (2 * S)) | c;
+                        left &= left - 1;
+                    }
                     nob += static_cast<uint32_t>(__builtin_popcountll(hm));
                     if (nob > PMS_OUTBUF - 64u) {
                         uint64_t base = 0;
@@ -336,20 +405,45 @@ pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
                   static_cast<unsigned long long>(batches));
 }
 
+}  // namespace
+
+extern "C" __global__ void __launch_bounds__(1024)
+pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
+                        const pms_work_item* __restrict__ work, uint32_t n_work,
+                        pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
+                        uint32_t q_words) {
+    search_groups<2>(insts, work, n_work, state, ctr, q_words);
+}
+
+// At most 4 wavefronts per workgroup: the 64 accumulators per lane need more
+// than the 128 VGPRs a 16-wavefront workgroup could give each lane.
+extern "C" __global__ void __launch_bounds__(PMS_GROUP64_MAX_THREADS)
+pms_search_group64_kernel(const pms_dev_instance* __restrict__ insts,
+                          const pms_work_item* __restrict__ work, uint32_t n_work,
+                          pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
+                          uint32_t q_words) {
+    search_groups<3>(insts, work, n_work, state, ctr, q_words);
+}
+
 namespace pms {
 
 hipError_t launch_search_group(const pms_dev_instance* insts, const pms_work_item* work,
                                uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
                                uint32_t q_words, uint32_t grid, uint32_t wg_waves,
-                               hipStream_t stream) {
+                               hipStream_t stream, int suffix) {
     const size_t lds = static_cast<size_t>(wg_waves) * (q_words + PMS_OUTBUF) * sizeof(uint32_t);
-    hipLaunchKernelGGL(pms_search_group_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream, insts,
-                       work, n_work, state, ctr, q_words);
+    if (suffix == 3)
+        hipLaunchKernelGGL(pms_search_group64_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream,
+                           insts, work, n_work, state, ctr, q_words);
+    else
+        hipLaunchKernelGGL(pms_search_group_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream,
+                           insts, work, n_work, state, ctr, q_words);
     return hipGetLastError();
 }
 
-const void* search_group_kernel_symbol() {
-    return reinterpret_cast<const void*>(&pms_search_group_kernel);
+const void* search_group_kernel_symbol(int suffix) {
+    return suffix == 3 ? reinterpret_cast<const void*>(&pms_search_group64_kernel)
+                       : reinterpret_cast<const void*>(&pms_search_group_kernel);
 }
 
 }  // namespace pms

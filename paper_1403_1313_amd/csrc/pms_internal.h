@@ -13,6 +13,8 @@
 #define PMS_QCAP 128u
 // Per-wavefront staging slots for final survivors (flushed at > OUTBUF-64).
 #define PMS_OUTBUF 256u
+// Largest workgroup of the 64-candidates-per-lane kernel (4 wavefronts).
+#define PMS_GROUP64_MAX_THREADS 256
 
 // One row for the window-building kernel.
 typedef struct {
@@ -36,22 +38,29 @@ hipError_t launch_fill(uint32_t* p, uint64_t words, uint32_t v, hipStream_t stre
 
 const void* search_kernel_symbol();
 
+// suffix: 2 (16 candidates per lane) or 3 (64).
 hipError_t launch_search_group(const pms_dev_instance* insts, const pms_work_item* work,
                                uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
                                uint32_t q_words, uint32_t grid, uint32_t wg_waves,
-                               hipStream_t stream);
+                               hipStream_t stream, int suffix);
 
-const void* search_group_kernel_symbol();
+const void* search_group_kernel_symbol(int suffix);
 
 hipError_t valu_probe(int op, uint32_t blocks, uint32_t iters, uint32_t* sink, uint64_t* clocks,
                       hipStream_t s);
 
 // LDS words of stage queues one wavefront needs for instances of up to
-// max_n sequences: LANE keeps one uint32 candidate per slot, GROUP a uint32
-// prefix and a uint16 alive mask.
-inline uint32_t queue_words(int32_t max_n, bool group) {
+// max_n sequences.  variant: LANE keeps one uint32 candidate per slot, GROUP
+// a uint32 prefix and a uint32 alive mask, GROUP64 a prefix and a uint64 mask.
+inline uint32_t queue_words(int32_t max_n, uint32_t variant) {
     const uint32_t stages = static_cast<uint32_t>(max_n > 1 ? max_n - 1 : 0);
-    return stages * (group ? PMS_QCAP + PMS_QCAP / 2 : PMS_QCAP);
+    const uint32_t words = variant == PMS_VARIANT_GROUP64 ? 3u : variant == PMS_VARIANT_GROUP ? 2u : 1u;
+    return stages * words * PMS_QCAP;
+}
+
+// Candidates per lane of a variant.
+inline uint32_t candidates_per_lane(uint32_t variant) {
+    return variant == PMS_VARIANT_GROUP64 ? 64u : variant == PMS_VARIANT_GROUP ? 16u : 1u;
 }
 
 }  // namespace pms

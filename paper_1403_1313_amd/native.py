@@ -43,7 +43,8 @@ class Result(ctypes.Structure):
                 ("count", ctypes.c_uint64), ("latency_ms", ctypes.c_double)]
 
 
-VARIANT_AUTO, VARIANT_LANE, VARIANT_GROUP = 0, 1, 2
+VARIANT_AUTO, VARIANT_LANE, VARIANT_GROUP, VARIANT_GROUP64 = 0, 1, 2, 3
+VARIANT_NAMES = {1: "lane", 2: "group16", 3: "group64"}
 LAYOUT_PLANES, LAYOUT_BITSLICED = 0, 1
 
 

@@ -123,9 +123,9 @@ class Server:
         self.items_per_step = int(items_per_step)
         self.copy_stream = torch.cuda.Stream(self.dev)
         self.max_inflight = int(max_inflight)
-        # Steps run the grouped kernel, whose windows are bit-sliced.
+        # Steps run a grouped kernel, whose windows are bit-sliced: 64
+        # candidates per lane, or 16 when a step holds an l = 2 request.
         self.config = dict(config or {})
-        self.config["variant"] = nat.VARIANT_GROUP
         self.reserve = reserve  # fixed first output reservation (tests of the rerun path)
         self.d_insts = torch.zeros(MAX_SLOTS * 40, dtype=torch.uint8, device=self.dev)
         self.d_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8, device=self.dev)
@@ -310,11 +310,14 @@ class Server:
         self.idle_bufs.pop()
         torch = self.torch
         max_n = max(r.n for r in buf.reqs)
+        cfg = dict(self.config)
+        if "variant" not in cfg:
+            cfg["variant"] = nat.VARIANT_GROUP64 if min(r.l for r in buf.reqs) >= 3 else nat.VARIANT_GROUP
         with torch.cuda.stream(self.stream):
             buf.d_work[:n_items * 16].copy_(buf.h_work[:n_items * 16], non_blocking=True)
             buf.d_ctr.zero_()
         nat.step_launch(self.d_insts, MAX_SLOTS, max_n, buf.d_work, n_items, self.d_state,
-                        buf.d_ctr, config=self.config, stream=self.stream)
+                        buf.d_ctr, config=cfg, stream=self.stream)
         with torch.cuda.stream(self.stream):
             buf.h_state.copy_(self.d_state, non_blocking=True)
             buf.event = torch.cuda.Event()

@@ -157,7 +157,7 @@ def test_config_validation():
     assert nat.get_config() == {"chunk": 16384, "wg_waves": 4, "wgs_per_cu": 0, "tail_split": 8,
                                 "variant": 0}
     with pytest.raises(nat.PmsError):
-        nat.set_config(variant=3)
+        nat.set_config(variant=4)
 
 
 def test_injected_failure_propagates(monkeypatch):

@@ -36,10 +36,11 @@ def gpu_solve(nat, seqs, l, d):
     return res, nat.last_stats()
 
 
-@pytest.fixture(params=["lane", "group"])
+@pytest.fixture(params=["lane", "group16", "group64"])
 def variant(request, nat):
     """Runs a test once per search kernel variant."""
-    v = {"lane": nat.VARIANT_LANE, "group": nat.VARIANT_GROUP}[request.param]
+    v = {"lane": nat.VARIANT_LANE, "group16": nat.VARIANT_GROUP,
+         "group64": nat.VARIANT_GROUP64}[request.param]
     nat.set_config(variant=v)
     yield v
     nat.set_config(reset=True)
@@ -204,7 +205,7 @@ def test_launch_configurations_agree(nat):
     inst = fmgen.gen_fm(11, 3, 20, 600, 0)
     want = oracle.solve(inst.seqs, 11, 3, mode="skip", return_visits=True)
     try:
-        for var in (nat.VARIANT_LANE, nat.VARIANT_GROUP):
+        for var in (nat.VARIANT_LANE, nat.VARIANT_GROUP, nat.VARIANT_GROUP64):
             for chunk in (64, 1024, 16384, 1 << 16):
                 for waves in (1, 2, 4, 8, 16):
                     for tail in (0, 8, 64):
