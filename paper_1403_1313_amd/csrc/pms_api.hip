@@ -236,10 +236,11 @@ struct Ctx {
     int device = 0;
     int cus = 0;
     size_t lds_per_block = 65536;
+    size_t lds_per_cu = 65536;
     std::string arch;
     hipStream_t stream = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    DevBuf d_raw, d_win, d_out, d_meta;
+    DevBuf d_raw, d_win, d_out, d_meta, d_gq;
     HostBuf h_raw, h_meta, h_back;
     pms_config cfg = default_config();
     pms_stats last{};
@@ -249,7 +250,7 @@ struct Ctx {
     hipGraphExec_t gexec = nullptr;
     std::string gsig;
     // device-level workspace for pms_solve_dev
-    DevBuf dv_win, dv_meta;
+    DevBuf dv_win, dv_meta, dv_gq;
     HostBuf hv_meta;
     hipEvent_t dv_copied = nullptr;
     bool dv_copy_live = false;
@@ -281,6 +282,8 @@ int init_ctx(Ctx& c) {
     c.device = dev;
     c.cus = prop.multiProcessorCount;
     c.lds_per_block = prop.sharedMemPerBlock;
+    c.lds_per_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
+                                                         : prop.sharedMemPerBlock;
     c.arch = prop.gcnArchName;
     PMS_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
     for (auto& e2 : c.ev) PMS_HIP(hipEventCreate(&e2));
@@ -290,25 +293,55 @@ int init_ctx(Ctx& c) {
 }
 
 // Workgroup shape and grid for a search launch.
-int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, uint32_t* grid,
-                 uint32_t* waves, uint32_t* q_words) {
-    const uint32_t qw = pms::queue_words(max_n, variant);
-    const size_t per_wave = static_cast<size_t>(qw + PMS_OUTBUF) * sizeof(uint32_t);
+// Shape of one search launch.
+struct Shape2 {
+    uint32_t grid = 0, waves = 0;
+    uint32_t q_words = 0;          // per-lane kernel: LDS queue words per wavefront
+    pms::GroupQueues gq{0, nullptr, 0};
+};
+
+// Workgroup shape, grid and queue placement for a search launch.  The
+// grouped kernels keep as many stage queues in LDS as the occupancy their
+// registers allow leaves room for, and the rest in `ws` (grown as needed).
+int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, DevBuf& ws,
+                 Shape2* out) {
+    const uint32_t stages = static_cast<uint32_t>(max_n > 1 ? max_n - 1 : 0);
+    const void* fn = variant == PMS_VARIANT_LANE
+                         ? pms::search_kernel_symbol()
+                         : pms::search_group_kernel_symbol(variant == PMS_VARIANT_GROUP64 ? 3 : 2);
+    uint32_t lds_stages = stages, gq_words = 0;
+    size_t per_wave;
+    if (variant == PMS_VARIANT_LANE) {
+        per_wave = static_cast<size_t>(pms::queue_words(max_n, variant) + PMS_OUTBUF) * 4;
+    } else {
+        const uint32_t entry = variant == PMS_VARIANT_GROUP64 ? 3u : 2u;
+        hipFuncAttributes attr;
+        PMS_HIP(hipFuncGetAttributes(&attr, fn));
+        const int vgprs = std::max(attr.numRegs, 8);
+        const int per_simd = std::max(1, std::min(8, 512 / ((vgprs + 7) / 8 * 8)));
+        const size_t budget = c.lds_per_cu / (4 * static_cast<size_t>(per_simd));
+        const size_t fit = budget / 4 > PMS_OUTBUF ? (budget / 4 - PMS_OUTBUF) / (entry * PMS_QCAP) : 0;
+        lds_stages = std::min<uint32_t>(stages, static_cast<uint32_t>(fit));
+        gq_words = (stages - lds_stages) * entry * PMS_QCAP;
+        per_wave = static_cast<size_t>(lds_stages * entry * PMS_QCAP + PMS_OUTBUF) * 4;
+    }
     uint32_t w = cfg.wg_waves;
     if (variant == PMS_VARIANT_GROUP64) w = std::min<uint32_t>(w, PMS_GROUP64_MAX_THREADS / 64);
     while (w > 1 && per_wave * w > c.lds_per_block) --w;
     if (per_wave * w > c.lds_per_block)
         return fail(PMS_ERR_INVALID, "stage queues exceed the LDS of one workgroup");
     int per_cu = 0;
-    const void* fn = variant == PMS_VARIANT_LANE
-                         ? pms::search_kernel_symbol()
-                         : pms::search_group_kernel_symbol(variant == PMS_VARIANT_GROUP64 ? 3 : 2);
     PMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * w, per_wave * w));
     if (per_cu < 1) per_cu = 1;
     if (cfg.wgs_per_cu > 0 && static_cast<int>(cfg.wgs_per_cu) < per_cu) per_cu = cfg.wgs_per_cu;
-    *grid = static_cast<uint32_t>(per_cu * c.cus);
-    *waves = w;
-    *q_words = qw;
+    out->grid = static_cast<uint32_t>(per_cu * c.cus);
+    out->waves = w;
+    out->q_words = variant == PMS_VARIANT_LANE ? pms::queue_words(max_n, variant) : 0;
+    out->gq = {lds_stages, nullptr, gq_words};
+    if (gq_words) {
+        PMS_TRY(ws.ensure(static_cast<size_t>(out->grid) * w * gq_words * 4));
+        out->gq.gq = ws.as<uint32_t>();
+    }
     return PMS_OK;
 }
 
@@ -446,17 +479,15 @@ int stage_batch(Ctx& c, Batch& b) {
 
 hipError_t launch_variant(uint32_t variant, const pms_dev_instance* insts,
                           const pms_work_item* work, uint32_t n_work, pms_dev_state* state,
-                          pms_dev_counters* ctr, uint32_t qw, uint32_t grid, uint32_t waves,
-                          hipStream_t s) {
+                          pms_dev_counters* ctr, const Shape2& sh, hipStream_t s) {
     if (variant == PMS_VARIANT_LANE)
-        return pms::launch_search(insts, work, n_work, state, ctr, qw, grid, waves, s);
-    return pms::launch_search_group(insts, work, n_work, state, ctr, qw, grid, waves, s,
+        return pms::launch_search(insts, work, n_work, state, ctr, sh.q_words, sh.grid, sh.waves, s);
+    return pms::launch_search_group(insts, work, n_work, state, ctr, sh.gq, sh.grid, sh.waves, s,
                                     variant == PMS_VARIANT_GROUP64 ? 3 : 2);
 }
 
 // Enqueues copy-in, both kernels and copy-back of the state block on c.stream.
-int enqueue_batch(Ctx& c, const Batch& b, bool timed, uint32_t grid, uint32_t waves,
-                  uint32_t qw) {
+int enqueue_batch(Ctx& c, const Batch& b, bool timed, const Shape2& sh) {
     char* dm = c.d_meta.as<char>();
     PMS_HIP(hipMemcpyAsync(c.d_raw.p, c.h_raw.p, b.raw_bytes, hipMemcpyHostToDevice, c.stream));
     PMS_HIP(hipMemcpyAsync(dm, c.h_meta.p, b.meta_bytes, hipMemcpyHostToDevice, c.stream));
@@ -470,8 +501,7 @@ int enqueue_batch(Ctx& c, const Batch& b, bool timed, uint32_t grid, uint32_t wa
                            reinterpret_cast<const pms_work_item*>(dm + b.off_work),
                            static_cast<uint32_t>(b.work.size()),
                            reinterpret_cast<pms_dev_state*>(dm + b.off_state),
-                           reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves,
-                           c.stream));
+                           reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), sh, c.stream));
     if (timed) PMS_HIP(hipEventRecord(c.ev[2], c.stream));
     PMS_HIP(hipMemcpyAsync(c.h_back.as<char>(b.off_state), dm + b.off_state,
                            b.meta_bytes - b.off_state, hipMemcpyDeviceToHost, c.stream));
@@ -491,17 +521,20 @@ std::string graph_signature(const Ctx& c, const Batch& b, const pms_config& cfg)
 
 // Runs a staged batch: eagerly (timed with events) or through the graph.
 int run_batch(Ctx& c, Batch& b, const pms_config& cfg, bool use_graph) {
-    uint32_t grid = 0, waves = 0, qw = 0;
-    PMS_TRY(launch_shape(c, cfg, b.max_n, b.variant, &grid, &waves, &qw));
+    Shape2 sh;
+    PMS_TRY(launch_shape(c, cfg, b.max_n, b.variant, c.d_gq, &sh));
+    const uint32_t grid = sh.grid, waves = sh.waves;
     if (use_graph) {
-        const std::string sig = graph_signature(c, b, cfg);
+        const std::string sig = graph_signature(c, b, cfg) + ":" +
+                                std::to_string(reinterpret_cast<uintptr_t>(sh.gq.gq)) + ":" +
+                                std::to_string(sh.gq.lds_stages) + ":" + std::to_string(grid);
         if (!c.gexec || sig != c.gsig) {
             if (c.gexec) {
                 (void)hipGraphExecDestroy(c.gexec);
                 c.gexec = nullptr;
             }
             PMS_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
-            const int s = enqueue_batch(c, b, false, grid, waves, qw);
+            const int s = enqueue_batch(c, b, false, sh);
             hipGraph_t graph = nullptr;
             const hipError_t e = hipStreamEndCapture(c.stream, &graph);
             if (s != PMS_OK) {
@@ -523,7 +556,7 @@ int run_batch(Ctx& c, Batch& b, const pms_config& cfg, bool use_graph) {
         c.last.kernel_ms = ms;  // whole graph: copies + both kernels
         c.last.windows_ms = 0;
     } else {
-        PMS_TRY(enqueue_batch(c, b, true, grid, waves, qw));
+        PMS_TRY(enqueue_batch(c, b, true, sh));
         PMS_HIP(hipStreamSynchronize(c.stream));
         float w_ms = 0, k_ms = 0;
         PMS_HIP(hipEventElapsedTime(&w_ms, c.ev[0], c.ev[1]));
@@ -931,13 +964,14 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
     const pms_config r = resolve(cfg, c.cfg);
     if (!config_ok(r)) return fail(PMS_ERR_INVALID, "configuration field out of range");
     const uint32_t variant = r.variant == PMS_VARIANT_AUTO ? PMS_VARIANT_GROUP64 : r.variant;
-    uint32_t grid = 0, waves = 0, qw = 0;
-    PMS_TRY(launch_shape(c, r, max_n, variant, &grid, &waves, &qw));
+    Shape2 sh;
+    PMS_TRY(launch_shape(c, r, max_n, variant, c.dv_gq, &sh));
+    const uint32_t grid = sh.grid, waves = sh.waves;
     hipStream_t s = static_cast<hipStream_t>(stream);
     PMS_HIP(hipEventRecord(c.ev[0], s));
     PMS_HIP(hipEventRecord(c.ev[1], s));
     PMS_HIP(launch_variant(variant, dev_instances, dev_work, static_cast<uint32_t>(n_work), dev_state,
-                           dev_counters, qw, grid, waves, s));
+                           dev_counters, sh, s));
     PMS_HIP(hipEventRecord(c.ev[2], s));
     c.last = pms_stats{};
     c.last.grid = grid;
@@ -964,8 +998,9 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     b.shape = {Shape{n, t, l, d}};
     b.out_cap = {capacity > 0 ? capacity : 1};
     plan_batch(b, cfg, target_items(c));
-    uint32_t grid = 0, waves = 0, qw = 0;
-    PMS_TRY(launch_shape(c, cfg, b.max_n, b.variant, &grid, &waves, &qw));
+    Shape2 sh;
+    PMS_TRY(launch_shape(c, cfg, b.max_n, b.variant, c.dv_gq, &sh));
+    const uint32_t grid = sh.grid, waves = sh.waves;
     if (c.dv_copy_live) PMS_HIP(hipEventSynchronize(c.dv_copied));
     PMS_TRY(c.dv_win.ensure(std::max<size_t>(b.win_words * 4, 256)));
     PMS_TRY(c.dv_meta.ensure(b.meta_bytes));
@@ -997,7 +1032,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
                            reinterpret_cast<const pms_work_item*>(dm + b.off_work),
                            static_cast<uint32_t>(b.work.size()),
                            reinterpret_cast<pms_dev_state*>(dm + b.off_state),
-                           reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), qw, grid, waves, s));
+                           reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), sh, s));
     PMS_HIP(hipEventRecord(c.ev[2], s));
     PMS_HIP(hipMemcpyAsync(dev_count, dm + b.off_state + offsetof(pms_dev_state, count),
                            sizeof(uint64_t), hipMemcpyDeviceToDevice, s));

@@ -227,26 +227,35 @@ __device__ __forceinline__ typename MaskOf<S>::type scan_group_any(
 }
 
 // Persistent grouped search; S = 2 (16 candidates per lane) or 3 (64).
+// Stage queues for stages 1..lds_stages live in LDS; deeper stages (rarely
+// reached, so rarely touched) live in a per-wavefront region of the global
+// workspace `gq` (gq_words words per wavefront), which leaves room in LDS for
+// more resident wavefronts.
 template <int S>
 __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict__ insts,
                                               const pms_work_item* __restrict__ work,
                                               uint32_t n_work, pms_dev_state* __restrict__ state,
                                               pms_dev_counters* __restrict__ ctr,
-                                              uint32_t q_words) {
+                                              uint32_t lds_stages, uint32_t* __restrict__ gq,
+                                              uint32_t gq_words) {
     typedef typename MaskOf<S>::type Mask;
     constexpr int K = 1 << (2 * S);
     constexpr uint32_t kNone = 0xffffffffu;
     constexpr Mask kAll = static_cast<Mask>(~static_cast<Mask>(0)) >> (8 * sizeof(Mask) - K);
+    constexpr uint32_t kEntryWords = 1 + sizeof(Mask) / 4;
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
     const uint32_t wave = uni(threadIdx.x >> 6);
-    // Per wavefront: queue prefixes [stages][QCAP] u32, queue masks
-    // [stages][QCAP] Mask, survivor staging [OUTBUF] u32.
+    // Per wavefront in LDS: queue prefixes [lds_stages][QCAP] u32, masks
+    // [lds_stages][QCAP] Mask, survivor staging [OUTBUF] u32.  In the
+    // workspace: per deeper stage, prefixes [QCAP] u32 then masks [QCAP] Mask.
+    const uint32_t q_words = lds_stages * kEntryWords * PMS_QCAP;
     uint32_t* const qp = lds + wave * (q_words + PMS_OUTBUF);
-    constexpr uint32_t kEntryWords = 1 + sizeof(Mask) / 4;
-    const uint32_t stages_cap = q_words / (kEntryWords * PMS_QCAP);
-    Mask* const qm = reinterpret_cast<Mask*>(qp + stages_cap * PMS_QCAP);
+    Mask* const qm = reinterpret_cast<Mask*>(qp + lds_stages * PMS_QCAP);
     uint32_t* const ob = qp + q_words;
+    const uint32_t gwave = blockIdx.x * uni(blockDim.x >> 6) + wave;
+    uint32_t* const gw = gq + static_cast<size_t>(gwave) * gq_words;
+    const uint32_t stages_cap = lds_stages + gq_words / (kEntryWords * PMS_QCAP);
 
     uint32_t cur = kNone, pending = 0, stash = kNone;
     bool more = true;
@@ -269,9 +278,17 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         if (full) {
             s = 63u - static_cast<uint32_t>(__builtin_clzll(full));
             const uint32_t c = __builtin_amdgcn_readlane(counts, s);
-            const uint32_t at = (s - 1) * PMS_QCAP + c - 64u + lane;
-            prefix = qp[at];
-            alive = qm[at];
+            const uint32_t at = c - 64u + lane;
+            const uint32_t row = s - 1;
+            if (row < lds_stages) {
+                prefix = qp[row * PMS_QCAP + at];
+                alive = qm[row * PMS_QCAP + at];
+            } else {
+                const uint32_t* g = gw + (row - lds_stages) * kEntryWords * PMS_QCAP;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                prefix = g[at];
+                alive = reinterpret_cast<const Mask*>(g + PMS_QCAP)[at];
+            }
             if (lane == s) counts -= 64u;
         } else if (next < end) {
             s = 0;
@@ -350,9 +367,19 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             }
             s = static_cast<uint32_t>(__builtin_ctzll(nz));
             const uint32_t c = __builtin_amdgcn_readlane(counts, s);
-            if (lane < c) {
-                prefix = qp[(s - 1) * PMS_QCAP + lane];
-                alive = qm[(s - 1) * PMS_QCAP + lane];
+            const uint32_t row = s - 1;
+            if (row < lds_stages) {
+                if (lane < c) {
+                    prefix = qp[row * PMS_QCAP + lane];
+                    alive = qm[row * PMS_QCAP + lane];
+                }
+            } else {
+                const uint32_t* g = gw + (row - lds_stages) * kEntryWords * PMS_QCAP;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                if (lane < c) {
+                    prefix = g[lane];
+                    alive = reinterpret_cast<const Mask*>(g + PMS_QCAP)[lane];
+                }
             }
             if (lane == s) counts = 0;
         }
@@ -367,9 +394,19 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             if (s + 1 < n) {
                 const uint32_t base = __builtin_amdgcn_readlane(counts, s + 1);
                 const uint32_t r = rank_below(pm);
-                if (keep) {
-                    qp[s * PMS_QCAP + base + r] = prefix;
-                    qm[s * PMS_QCAP + base + r] = pass;
+                const uint32_t row = s;
+                if (row < lds_stages) {
+                    if (keep) {
+                        qp[row * PMS_QCAP + base + r] = prefix;
+                        qm[row * PMS_QCAP + base + r] = pass;
+                    }
+                } else {
+                    uint32_t* g = gw + (row - lds_stages) * kEntryWords * PMS_QCAP;
+                    if (keep) {
+                        g[base + r] = prefix;
+                        reinterpret_cast<Mask*>(g + PMS_QCAP)[base + r] = pass;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 }
                 if (lane == s + 1) counts += static_cast<uint32_t>(__builtin_popcountll(pm));
             } else {
@@ -411,8 +448,8 @@ extern "C" __global__ void __launch_bounds__(1024)
 pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
                         const pms_work_item* __restrict__ work, uint32_t n_work,
                         pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
-                        uint32_t q_words) {
-    search_groups<2>(insts, work, n_work, state, ctr, q_words);
+                        uint32_t lds_stages, uint32_t* __restrict__ gq, uint32_t gq_words) {
+    search_groups<2>(insts, work, n_work, state, ctr, lds_stages, gq, gq_words);
 }
 
 // At most 4 wavefronts per workgroup: the 64 accumulators per lane need more
@@ -421,23 +458,25 @@ extern "C" __global__ void __launch_bounds__(PMS_GROUP64_MAX_THREADS)
 pms_search_group64_kernel(const pms_dev_instance* __restrict__ insts,
                           const pms_work_item* __restrict__ work, uint32_t n_work,
                           pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
-                          uint32_t q_words) {
-    search_groups<3>(insts, work, n_work, state, ctr, q_words);
+                          uint32_t lds_stages, uint32_t* __restrict__ gq, uint32_t gq_words) {
+    search_groups<3>(insts, work, n_work, state, ctr, lds_stages, gq, gq_words);
 }
 
 namespace pms {
 
 hipError_t launch_search_group(const pms_dev_instance* insts, const pms_work_item* work,
                                uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
-                               uint32_t q_words, uint32_t grid, uint32_t wg_waves,
+                               const GroupQueues& q, uint32_t grid, uint32_t wg_waves,
                                hipStream_t stream, int suffix) {
-    const size_t lds = static_cast<size_t>(wg_waves) * (q_words + PMS_OUTBUF) * sizeof(uint32_t);
+    const uint32_t entry = suffix == 3 ? 3u : 2u;
+    const size_t lds = static_cast<size_t>(wg_waves) *
+                       (q.lds_stages * entry * PMS_QCAP + PMS_OUTBUF) * sizeof(uint32_t);
     if (suffix == 3)
         hipLaunchKernelGGL(pms_search_group64_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream,
-                           insts, work, n_work, state, ctr, q_words);
+                           insts, work, n_work, state, ctr, q.lds_stages, q.gq, q.gq_words);
     else
         hipLaunchKernelGGL(pms_search_group_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream,
-                           insts, work, n_work, state, ctr, q_words);
+                           insts, work, n_work, state, ctr, q.lds_stages, q.gq, q.gq_words);
     return hipGetLastError();
 }
 

@@ -38,10 +38,18 @@ hipError_t launch_fill(uint32_t* p, uint64_t words, uint32_t v, hipStream_t stre
 
 const void* search_kernel_symbol();
 
+// Where a grouped launch keeps its stage queues: the first lds_stages in LDS,
+// the rest in gq (gq_words words per wavefront, grid x wg_waves wavefronts).
+struct GroupQueues {
+    uint32_t lds_stages;
+    uint32_t* gq;
+    uint32_t gq_words;
+};
+
 // suffix: 2 (16 candidates per lane) or 3 (64).
 hipError_t launch_search_group(const pms_dev_instance* insts, const pms_work_item* work,
                                uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
-                               uint32_t q_words, uint32_t grid, uint32_t wg_waves,
+                               const GroupQueues& q, uint32_t grid, uint32_t wg_waves,
                                hipStream_t stream, int suffix);
 
 const void* search_group_kernel_symbol(int suffix);
