@@ -160,7 +160,7 @@ def bench_plain(args):
             parity = [nat.decode(int(c), l) for c in codes] == recs[0]["motifs"] and \
                 st["seq_visits"] == recs[0]["skip_visits"]
 
-    traffic = rec["bytes_per_launch"] if (rec and fresh) else None
+    traffic = rec.get("bytes_per_launch") if (rec and fresh) else None
     line = {
         "metric": "candidates/s",
         "value": cands / (ms_step * 1e-3),
