@@ -13,6 +13,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -79,14 +80,21 @@ def cpu_baseline(seqs, l, d, target_s):
                       f"({span / 4 ** l:.2e} of 4^{l}), {dt:.1f} s on {threads} host threads"}
 
 
+def code_text(src):
+    """Source text without // comments and blank lines: a comment edit leaves
+    the counter record of a kernel valid."""
+    lines = (re.sub(r"//.*", "", ln).rstrip() for ln in src.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def load_counters(path, key, source):
     """Counter record for `key` and whether the kernel source still matches it."""
     import hashlib
     try:
         with open(path) as f:
             rec = json.load(f).get(key)
-        with open(os.path.join(ROOT, "paper_1403_1313_amd", "csrc", source), "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        with open(os.path.join(ROOT, "paper_1403_1313_amd", "csrc", source)) as f:
+            h = hashlib.sha256(code_text(f.read()).encode()).hexdigest()[:16]
     except (OSError, ValueError):
         return None, False
     if not rec:

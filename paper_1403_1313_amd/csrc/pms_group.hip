@@ -3,28 +3,28 @@
 // The same enumeration and the same enhanced rule as pms_search_kernel, with
 // the window index bit-sliced instead of the candidate:
 //
-//  * A lane owns a *group*: the 16 candidates that share their first l-2
-//    bases (the prefix).  Candidate c of the group has bases c >> 2 and c & 3
-//    at positions l-2 and l-1, so its motif code is (group << 4) | c and
-//    groups are numbered in dictionary order.
+//  * A lane owns a *group*: the 4^S candidates that share their first
+//    P = l - S bases (the prefix); S = 2 (16 per group) or S = 3 (64).
+//    Candidate c of the group has the base-4 digits of c at the last S
+//    positions, so its motif code is (group << 2S) | c and groups are
+//    numbered in dictionary order.
 //  * Windows are processed 32 at a time: for each position p the window table
 //    holds two words whose bit j is the high / low bit of the base at
 //    position p of window j (pms_windows_kernel, bit-sliced layout).  A
 //    mismatch vector is (WH ^ CH) | (WL ^ CL) with CH, CL all-ones or all-zero
 //    masks of the lane's prefix base.
 //  * The prefix positions' mismatch vectors are added by a carry-save tree
-//    into a 4-bit bit-sliced count c (32 windows per register).  Shared by the
-//    16 candidates of the group, that count is computed once.  The last two
-//    positions contribute s in {0, 1, 2} mismatches, a wave-uniform function of
-//    the window and the candidate's two bases, so with u = [s >= 1],
-//    v = [s >= 2] (scalar ALU) and T_k = [c <= d - k] a window is within d of
-//    candidate c exactly when  T_2 | (T_1 & ~v) | (T_0 & ~u).  Per candidate
-//    and per 32 windows that is two v_and_or_b32.
+//    into a 4-bit bit-sliced count c (32 windows per register), computed once
+//    for the whole group, and compared with the thresholds T_k = [c <= d - k].
+//    The suffix positions' mismatch vectors depend only on the window, so
+//    they are wave-uniform (scalar unit); a selection tree over them decides
+//    [c + suffix mismatches <= d] for all 4^S candidates with plain
+//    and/or/not forms (scan_group).
 //  * The enhanced rule: after the windows of sequence s, a candidate with no
 //    window within d leaves the group's alive mask and is never examined for
 //    sequences s+1..; a group whose mask is empty is dropped, and the others
-//    go to an LDS queue for stage s+1 (ballot + mbcnt), deepest full queue
-//    first, exactly as in the per-lane kernel.
+//    go to a queue for stage s+1 (ballot + mbcnt), deepest full queue first,
+//    exactly as in the per-lane kernel.
 //  * Candidates alive after the last sequence are staged in LDS and flushed
 //    with one global atomicAdd per flush.
 
