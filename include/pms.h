@@ -174,6 +174,10 @@ typedef struct {
     uint32_t reruns;         /* relaunches caused by device output overflow */
     uint32_t variant;        /* pms_variant actually launched (LANE, GROUP or GROUP64) */
     uint32_t reserved;
+    double host_prep_ms;     /* host-level calls: validation, planning and staging before
+                                the launch (0 for device-level calls) */
+    double host_finish_ms;   /* host-level calls: copy-back, sort and capacity handling
+                                after the launch, reruns included (0 for device-level) */
 } pms_stats;
 
 int pms_last_stats(pms_stats* out);
@@ -295,8 +299,12 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
  * n*t bytes row-major on the device.  Motif codes are appended, unsorted, to
  * dev_out (capacity `capacity`); *dev_count (device uint64) receives |M|
  * (exact, also when it exceeds capacity).  Workspace is owned by the library
- * and reused; the call is asynchronous.  Invalid bytes are not checked
- * here (use pms_build_windows's flag or the host-level calls).
+ * and reused; the call is asynchronous.  Calls must be ordered: on one
+ * stream, or a later call on another stream only after the earlier one has
+ * completed.  A call with the same shape and configuration as the previous
+ * one reuses its window jobs and work table on the device and uploads only
+ * the per-call records.  Invalid bytes are not checked here (use
+ * pms_build_windows's flag or the host-level calls).
  */
 int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
                   uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count, void* stream);

@@ -41,6 +41,7 @@ def bench_batched(args):
     caps = [1 << 21] * len(insts)
     cache = os.environ.get("PMS_AUTOTUNE_CACHE") or os.path.join(ROOT, "gpurun_out", "autotune.json")
     os.makedirs(os.path.dirname(cache), exist_ok=True)
+    nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant])
     t0 = time.perf_counter()
     tuned = nat.autotune(20, 650, 13, 4, cache)
     tune_s = time.perf_counter() - t0
@@ -48,7 +49,7 @@ def bench_batched(args):
     for _ in range(max(1, args.warmup)):
         st, motifs, results = nat.solve_many(work, caps)
         assert st == nat.PMS_OK, nat.last_error()
-    walls, graph_ms, lat = [], [], []
+    walls, graph_ms, lat, prep_ms, finish_ms = [], [], [], [], []
     for _ in range(args.steps):
         w0 = time.perf_counter()
         st, motifs, results = nat.solve_many(work, caps)
@@ -56,6 +57,8 @@ def bench_batched(args):
         assert st == nat.PMS_OK, nat.last_error()
         s = nat.last_stats()
         graph_ms.append(s["kernel_ms"])
+        prep_ms.append(s["host_prep_ms"])
+        finish_ms.append(s["host_finish_ms"])
         lat.extend(r.latency_ms for r in results)
     stats = nat.last_stats()
     # One eager launch to split the search kernel from copies and windows.
@@ -107,6 +110,10 @@ def bench_batched(args):
         "candidates_per_s": cands / wall,
         "window_compares_per_s": stats["window_compares"] / wall,
         "graph_ms_median": float(np.median(graph_ms)),
+        "host_ms_median": {"prep": float(np.median(prep_ms)), "finish": float(np.median(finish_ms)),
+                           "binding": float(np.median(np.asarray(walls) * 1e3 - np.asarray(prep_ms)
+                                                      - np.asarray(graph_ms)
+                                                      - np.asarray(finish_ms)))},
         "eager": {"search_kernel_ms": eager["kernel_ms"], "windows_kernel_ms": eager["windows_ms"],
                   "variant": eager["variant"], "grid": eager["grid"], "wg_waves": eager["wg_waves"],
                   "slot_efficiency": eager["seq_visits"] / max(1, eager["candidate_slots"]),

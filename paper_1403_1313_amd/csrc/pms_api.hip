@@ -18,6 +18,7 @@
 #include <fstream>
 #include <mutex>
 #include <numeric>
+#include <chrono>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -241,7 +242,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     DevBuf d_raw, d_win, d_out, d_meta, d_gq;
-    HostBuf h_raw, h_meta, h_back;
+    HostBuf h_raw, h_meta, h_back, h_out;
     pms_config cfg = default_config();
     pms_stats last{};
     bool last_pending = false;     // last stats still need the event times
@@ -259,9 +260,22 @@ struct Ctx {
     int32_t dv_nw = 0;
     bool dv_counters = false;
     uint32_t dv_variant = PMS_VARIANT_LANE;
+    // pms_solve_dev plan of the last call: reused, and its window jobs and
+    // work table left on the device, while calls repeat the same shape and
+    // configuration and nothing else has written dv_meta.
+    Batch dv_plan;
+    std::string dv_key;
+    bool dv_plan_valid = false;
+    const void* dv_uploaded = nullptr;
+    // entry time of the current host-level call (host_prep_ms)
+    std::chrono::steady_clock::time_point t_call;
 };
 
 Ctx g_ctx;
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
 
 // About 32 work items per wavefront the device can hold resident.
 uint64_t target_items(const Ctx& c) { return static_cast<uint64_t>(std::max(c.cus, 1)) * 16u * 32u; }
@@ -592,7 +606,9 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     b.out_cap.assign(m, 0);
     plan_batch(b, cfg, target_items(c));
     PMS_TRY(stage_batch(c, b));
+    const double prep_ms = ms_since(c.t_call);
     PMS_TRY(run_batch(c, b, cfg, use_graph));
+    const auto t_back = std::chrono::steady_clock::now();
     counts.assign(m, 0);
     latency.assign(m, 0.0);
     status.assign(m, PMS_OK);
@@ -616,17 +632,21 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     c.last.batches = ctr->batches;
     c.last.candidate_slots = ctr->batches * 64u * pms::candidates_per_lane(b.variant);
     c.last.reruns = 0;
-    // Outputs larger than the device estimate: solve those again with the
-    // exact capacity (the count is exact, so one rerun suffices).
-    std::vector<std::vector<uint32_t>> host_out(m);
-    for (size_t i = 0; i < m; ++i) {
-        if (status[i] != PMS_OK || counts[i] > b.out_cap[i]) continue;
-        host_out[i].resize(counts[i]);
-        if (counts[i])
-            PMS_HIP(hipMemcpy(host_out[i].data(), c.d_out.as<uint32_t>() + b.out_off[i],
-                              counts[i] * 4, hipMemcpyDeviceToHost));
-    }
+    // Step a7.  Every instance's codes go to its segment of one pinned
+    // buffer: asynchronous copies, one synchronisation.  Outputs larger than
+    // the device estimate are solved again with the exact capacity (the count
+    // is exact, so one rerun suffices) once those copies have landed.
+    std::vector<size_t> seg(m + 1, 0);
+    for (size_t i = 0; i < m; ++i) seg[i + 1] = seg[i] + (status[i] == PMS_OK ? counts[i] : 0);
+    PMS_TRY(c.h_out.ensure(std::max<size_t>(seg[m] * 4, 256)));
+    uint32_t* const h_codes = c.h_out.as<uint32_t>();
+    for (size_t i = 0; i < m; ++i)
+        if (status[i] == PMS_OK && counts[i] && counts[i] <= b.out_cap[i])
+            PMS_HIP(hipMemcpyAsync(h_codes + seg[i], c.d_out.as<uint32_t>() + b.out_off[i],
+                                   counts[i] * 4, hipMemcpyDeviceToHost, c.stream));
+    PMS_HIP(hipStreamSynchronize(c.stream));
     for (size_t i : rerun) {
+        if (status[i] != PMS_OK) continue;
         Batch r;
         r.shape = {shapes[i]};
         r.rows = {rows[i]};
@@ -636,40 +656,41 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
         PMS_TRY(run_batch(c, r, cfg, false));
         const pms_dev_state* rs = c.h_back.as<pms_dev_state>(r.off_state);
         if (rs[0].count != counts[i]) return fail(PMS_ERR_DEVICE, "rerun changed the motif count");
-        host_out[i].resize(counts[i]);
-        PMS_HIP(hipMemcpy(host_out[i].data(), c.d_out.as<uint32_t>(), counts[i] * 4,
+        PMS_HIP(hipMemcpy(h_codes + seg[i], c.d_out.as<uint32_t>(), counts[i] * 4,
                           hipMemcpyDeviceToHost));
         c.last.reruns++;
     }
-    // Step a7: ascending order, then the caller's capacity; instances are
+    // Ascending order, then the caller's capacity; instances are
     // independent, so host threads take them in turn.
     std::atomic<size_t> next{0};
     std::atomic<bool> dup{false};
     auto worker = [&]() {
         for (size_t i = next++; i < m; i = next++) {
             if (status[i] != PMS_OK) continue;
-            std::vector<uint32_t>& v = host_out[i];
-            std::sort(v.begin(), v.end());
-            if (std::adjacent_find(v.begin(), v.end()) != v.end()) {
+            uint32_t* const v = h_codes + seg[i];
+            const size_t k_all = seg[i + 1] - seg[i];
+            std::sort(v, v + k_all);
+            if (std::adjacent_find(v, v + k_all) != v + k_all) {
                 dup = true;
                 continue;
             }
-            const uint64_t k = std::min<uint64_t>(caps[i], v.size());
-            if (k) memcpy(outs[i], v.data(), k * 4);
+            const uint64_t k = std::min<uint64_t>(caps[i], k_all);
+            if (k) memcpy(outs[i], v, k * 4);
         }
     };
-    uint64_t total = 0;
-    for (size_t i = 0; i < m; ++i) total += host_out[i].size();
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const unsigned nthreads = total < (1u << 16) ? 1u : std::min<unsigned>(std::min(hw, 16u), m);
+    const unsigned nthreads =
+        seg[m] < (1u << 16) ? 1u : std::min<unsigned>(std::min(hw, 16u), static_cast<unsigned>(m));
     std::vector<std::thread> pool;
     for (unsigned w = 1; w < nthreads; ++w) pool.emplace_back(worker);
     worker();
     for (auto& th : pool) th.join();
     if (dup) return fail(PMS_ERR_DEVICE, "duplicate motif in device output");
     for (size_t i = 0; i < m; ++i)
-        if (status[i] == PMS_OK && host_out[i].size() > caps[i])
+        if (status[i] == PMS_OK && counts[i] > caps[i])
             status[i] = fail(PMS_ERR_OVERFLOW, "more motifs than capacity");
+    c.last.host_prep_ms = prep_ms;
+    c.last.host_finish_ms = ms_since(t_back);
     return PMS_OK;
 }
 
@@ -815,6 +836,7 @@ int pms_get_config(pms_config* cfg) {
 
 int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t d,
               uint32_t* out_motifs, uint64_t* out_count) {
+    const auto t_call = std::chrono::steady_clock::now();
     g_last_error.clear();
     if (!out_count) return fail(PMS_ERR_INVALID, "out_count is NULL");
     const uint64_t cap = *out_count;
@@ -825,6 +847,7 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t 
     PMS_TRY(test_hook());
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     PMS_TRY(init_ctx(g_ctx));
+    g_ctx.t_call = t_call;
     std::vector<int> status;
     std::vector<uint64_t> counts;
     std::vector<double> lat;
@@ -835,6 +858,7 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t 
 }
 
 int pms_solve_many(const pms_instance* inst, int32_t count, pms_result* results) {
+    const auto t_call = std::chrono::steady_clock::now();
     g_last_error.clear();
     if (!inst || !results || count < 0) return fail(PMS_ERR_INVALID, "NULL batch or negative count");
     std::vector<Shape> shapes;
@@ -875,6 +899,7 @@ int pms_solve_many(const pms_instance* inst, int32_t count, pms_result* results)
     PMS_TRY(test_hook());
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     PMS_TRY(init_ctx(g_ctx));
+    g_ctx.t_call = t_call;
     std::vector<int> status;
     std::vector<uint64_t> counts;
     std::vector<double> lat;
@@ -938,6 +963,7 @@ int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, 
     const size_t bytes = align_up(static_cast<size_t>(n) * sizeof(pms_win_job), 256);
     PMS_TRY(c.hv_meta.ensure(bytes));
     PMS_TRY(c.dv_meta.ensure(bytes));
+    c.dv_plan_valid = false;  // dv_meta is about to hold other data
     pms_win_job* jobs = c.hv_meta.as<pms_win_job>();
     const int32_t stride = window_stride(t, l, layout);
     for (int32_t r = 0; r < n; ++r)
@@ -994,10 +1020,19 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     PMS_TRY(init_ctx(c));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const pms_config cfg = c.cfg;
-    Batch b;
-    b.shape = {Shape{n, t, l, d}};
-    b.out_cap = {capacity > 0 ? capacity : 1};
-    plan_batch(b, cfg, target_items(c));
+    std::ostringstream kss;
+    kss << n << ':' << t << ':' << l << ':' << d << ':' << cfg.chunk << ':' << cfg.wg_waves << ':'
+        << cfg.wgs_per_cu << ':' << cfg.tail_split << ':' << cfg.variant << ':' << target_items(c);
+    const std::string key = kss.str();
+    const bool reuse = c.dv_plan_valid && key == c.dv_key;
+    if (!reuse) {
+        c.dv_plan_valid = false;
+        c.dv_plan = Batch{};
+        c.dv_plan.shape = {Shape{n, t, l, d}};
+        c.dv_plan.out_cap = {1};
+        plan_batch(c.dv_plan, cfg, target_items(c));
+    }
+    const Batch& b = c.dv_plan;
     Shape2 sh;
     PMS_TRY(launch_shape(c, cfg, b.max_n, b.variant, c.dv_gq, &sh));
     const uint32_t grid = sh.grid, waves = sh.waves;
@@ -1007,7 +1042,11 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     PMS_TRY(c.hv_meta.ensure(b.meta_bytes));
     char* hm = c.hv_meta.as<char>();
     char* dm = c.dv_meta.as<char>();
-    memset(hm, 0, b.meta_bytes);
+    // The per-call records (instance; state, counters, flags) are rewritten
+    // every call; the window jobs and the work table only with a new plan.
+    const bool whole = !reuse || c.dv_uploaded != c.dv_meta.p;
+    memset(hm, 0, b.off_jobs);
+    memset(hm + b.off_state, 0, b.meta_bytes - b.off_state);
     pms_dev_instance* in = reinterpret_cast<pms_dev_instance*>(hm + b.off_insts);
     in->windows = c.dv_win.as<uint32_t>();
     in->out = dev_out;
@@ -1018,11 +1057,20 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     in->l = l;
     in->d = d;
     reinterpret_cast<pms_dev_state*>(hm + b.off_state)->items_left = b.items_per_inst[0];
-    memcpy(hm + b.off_jobs, b.jobs.data(), b.jobs.size() * sizeof(pms_win_job));
-    memcpy(hm + b.off_work, b.work.data(), b.work.size() * sizeof(pms_work_item));
-    PMS_HIP(hipMemcpyAsync(dm, hm, b.meta_bytes, hipMemcpyHostToDevice, s));
+    if (whole) {
+        memcpy(hm + b.off_jobs, b.jobs.data(), b.jobs.size() * sizeof(pms_win_job));
+        memcpy(hm + b.off_work, b.work.data(), b.work.size() * sizeof(pms_work_item));
+        PMS_HIP(hipMemcpyAsync(dm, hm, b.meta_bytes, hipMemcpyHostToDevice, s));
+    } else {
+        PMS_HIP(hipMemcpyAsync(dm, hm, b.off_jobs, hipMemcpyHostToDevice, s));
+        PMS_HIP(hipMemcpyAsync(dm + b.off_state, hm + b.off_state, b.meta_bytes - b.off_state,
+                               hipMemcpyHostToDevice, s));
+    }
     PMS_HIP(hipEventRecord(c.dv_copied, s));
     c.dv_copy_live = true;
+    c.dv_key = key;
+    c.dv_plan_valid = true;
+    c.dv_uploaded = c.dv_meta.p;
     PMS_HIP(hipEventRecord(c.ev[0], s));
     PMS_HIP(pms::launch_windows(reinterpret_cast<const pms_win_job*>(dm + b.off_jobs), n, t,
                                 dev_seqs, c.dv_win.as<uint32_t>(),

@@ -39,63 +39,61 @@ namespace {
 
 using namespace pms_dev;
 
-// Full adder on 32 bit-lanes: a + b + c = s + 2 * carry.
-__device__ __forceinline__ void full_add(uint32_t a, uint32_t b, uint32_t c, uint32_t& s,
-                                         uint32_t& carry) {
-    const uint32_t t = a ^ b;
-    s = t ^ c;
-    carry = (a & b) | (t & c);
+// Three-input bit functions as single v_bitop3_b32 instructions.  The
+// compiler would otherwise pick v_bfi / v_or3 / v_and_or forms for some of
+// them, which issue at half the rate of v_bitop3 on gfx950.  Truth-table
+// index: (a << 2) | (b << 1) | c.
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
 }
+constexpr uint32_t kXor3 = 0x96;     // a ^ b ^ c
+constexpr uint32_t kMaj = 0xE8;      // at least two of a, b, c
+constexpr uint32_t kMux = 0xCA;      // a ? b : c
+constexpr uint32_t kOrAndN = 0xF4;   // a | (b & ~c)
+constexpr uint32_t kOr3 = 0xFE;      // a | b | c
+constexpr uint32_t kAnd3 = 0x80;     // a & b & c
+constexpr uint32_t kNandOr = 0x1F;   // ~(a & (b | c))
+constexpr uint32_t kNorAnd = 0x07;   // ~(a | (b & c))
 
-// Bit-sliced count of P one-bit vectors: count = c1 + 2 c2 + 4 c4 + 8 c8
-// (P <= 15).  Column compression by full and half adders; every loop bound
-// and index is a compile-time constant once P is fixed.
+// Bit-sliced sum of P one-bit vectors plus a wave-uniform bias B < 32 given
+// as five all-ones / all-zero masks bias[i] = bit i of B:
+//   sum = c[0] + 2 c[1] + 4 c[2] + 8 c[3] + 16 c[4]   (P + B < 32).
+// Column compression by full adders (xor3 + majority) and half adders; every
+// loop bound and index is a compile-time constant once P is fixed.
 template <int P>
-__device__ __forceinline__ void count_bits(const uint32_t (&m)[P > 0 ? P : 1], uint32_t& c1,
-                                           uint32_t& c2, uint32_t& c4, uint32_t& c8) {
-    uint32_t w[4][16];
-    int nw[4] = {P, 0, 0, 0};
+__device__ __forceinline__ void count_bits(const uint32_t (&m)[P > 0 ? P : 1],
+                                           const uint32_t (&bias)[5], uint32_t (&c)[5]) {
+    uint32_t w[5][18];
+    int nw[5] = {P + 1, 1, 1, 1, 1};
 #pragma unroll
     for (int i = 0; i < P; ++i) w[0][i] = m[i];
+    w[0][P] = bias[0];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 1; k < 5; ++k) w[k][0] = bias[k];
 #pragma unroll
-        for (int it = 0; it < 16; ++it) {
+    for (int k = 0; k < 5; ++k) {
+#pragma unroll
+        for (int it = 0; it < 18; ++it) {
             if (nw[k] >= 3) {
-                uint32_t s, cy;
-                full_add(w[k][nw[k] - 3], w[k][nw[k] - 2], w[k][nw[k] - 1], s, cy);
+                const uint32_t x = w[k][nw[k] - 3], y = w[k][nw[k] - 2], z = w[k][nw[k] - 1];
                 nw[k] -= 2;
-                w[k][nw[k] - 1] = s;
-                if (k < 3) w[k + 1][nw[k + 1]++] = cy;
-            } else if (nw[k] == 2 && k < 3) {
-                const uint32_t a = w[k][0], b = w[k][1];
-                w[k][0] = a ^ b;
+                w[k][nw[k] - 1] = bop3<kXor3>(x, y, z);
+                if (k < 4) w[k + 1][nw[k + 1]++] = bop3<kMaj>(x, y, z);
+            } else if (nw[k] == 2 && k < 4) {
+                const uint32_t x = w[k][0], y = w[k][1];
+                w[k][0] = x ^ y;
                 nw[k] = 1;
-                w[k + 1][nw[k + 1]++] = a & b;
+                w[k + 1][nw[k + 1]++] = x & y;
             } else if (nw[k] == 2) {
-                // weight 8: two ones here would mean a count >= 16 > P
+                // weight 16: both set would mean a sum >= 32
                 w[k][0] |= w[k][1];
                 nw[k] = 1;
             }
         }
     }
-    c1 = nw[0] ? w[0][0] : 0u;
-    c2 = nw[1] ? w[1][0] : 0u;
-    c4 = nw[2] ? w[2][0] : 0u;
-    c8 = nw[3] ? w[3][0] : 0u;
-}
-
-// Bit-sliced [count <= k] for a wave-uniform k.
-__device__ __forceinline__ uint32_t count_le(uint32_t c1, uint32_t c2, uint32_t c4, uint32_t c8,
-                                             int k) {
-    if (k < 0) return 0u;
-    if (k >= 15) return ~0u;
-    uint32_t gt = 0u, eq = ~0u;
-    if (k & 8) { eq &= c8; } else { gt |= eq & c8; eq &= ~c8; }
-    if (k & 4) { eq &= c4; } else { gt |= eq & c4; eq &= ~c4; }
-    if (k & 2) { eq &= c2; } else { gt |= eq & c2; eq &= ~c2; }
-    if (k & 1) { /* eq &= c1; not needed */ } else { gt |= eq & c1; }
-    return ~gt;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) c[k] = nw[k] ? w[k][0] : 0u;
 }
 
 // A wave-uniform value copied into a VGPR.  VALU instructions that read an
@@ -116,9 +114,13 @@ template <> struct MaskOf<3> { typedef uint64_t type; };
 // window within d, restricted to `alive`.  W: the sequence's bit-sliced row
 // (groups x 2l words), wave-uniform.
 //
-// Per 32 windows: the prefix count c (carry-save tree), thresholds
-// T_k = [c <= d - k] for k = 0..S, then a selection tree over the suffix
-// positions: with s_q[b] = mismatch of base b at suffix position q,
+// Per 32 windows: the prefix mismatch count plus the bias 16 - d,
+// c' = c + 16 - d (< 32), so that the thresholds T_k = [c <= d - k] are
+// comparisons of c' with the constants 16 - k:
+//   T_0 = ~(c'16 & (c'8 | c'4 | c'2 | c'1)),  T_1 = ~c'16,
+//   T_2 = ~(c'16 | c'8 c'4 c'2 c'1),           T_3 = ~(c'16 | c'8 c'4 c'2),
+// then a selection tree over the suffix positions: with s_q[b] = mismatch of
+// base b at suffix position q,
 //   U_1[b1][k]    = s_1[b1] ? T[k+1] : T[k]                 k = 0..S-1
 //   U_j[..bj][k]  = s_j[bj] ? U_{j-1}[..][k+1] : U_{j-1}[..][k]
 // U_j[..][k] = [c + s_1 + .. + s_j <= d - k].  The last level is folded into
@@ -138,40 +140,66 @@ __device__ __forceinline__ typename MaskOf<S>::type scan_group(
         ch[p] = 0u - (b >> 1);
         cl[p] = 0u - (b & 1u);
     }
+    const uint32_t bias_value = static_cast<uint32_t>(16 - d);
+    uint32_t bias[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) bias[i] = to_vgpr(0u - ((bias_value >> i) & 1u));
     uint32_t found[K], top[N1];
 #pragma unroll
     for (int c = 0; c < K; ++c) found[c] = 0u;
 #pragma unroll
     for (int c = 0; c < N1; ++c) top[c] = 0u;
-    for (uint32_t gi = 0; gi < groups; ++gi, W += 2 * L) {
+    // The words of one group of 32 windows live in SGPRs.  The next group's
+    // words are requested as soon as the current ones have been consumed
+    // (prefix count and suffix vectors), so the scalar loads are in flight
+    // while the selection tree runs.
+    // (The first group is read through a volatile pointer so that the
+    // compiler does not merge these loads with the loop's and move them to
+    // the loop head.)
+    uint32_t w[2 * L];
+#pragma unroll
+    for (int i = 0; i < 2 * L; ++i) w[i] = ((__attribute__((address_space(4))) const volatile uint32_t*)W)[i];
+    for (uint32_t gi = 0; gi < groups; ++gi) {
         uint32_t m[P > 0 ? P : 1];
 #pragma unroll
-        for (int p = 0; p < P; ++p) m[p] = (W[p] ^ ch[p]) | (W[L + p] ^ cl[p]);
-        uint32_t c1 = 0, c2 = 0, c4 = 0, c8 = 0;
-        if (P > 0) count_bits<P>(m, c1, c2, c4, c8);
-        uint32_t t[S + 1];
-#pragma unroll
-        for (int k = 0; k <= S; ++k) t[k] = count_le(c1, c2, c4, c8, d - k);
+        for (int p = 0; p < P; ++p) m[p] = (w[p] ^ ch[p]) | (w[L + p] ^ cl[p]);
+        uint32_t c[5];
+        count_bits<P>(m, bias, c);
+        uint32_t t[4];
+        t[0] = bop3<kNandOr>(c[4], bop3<kOr3>(c[3], c[2], c[1]), c[0]);
+        t[1] = ~c[4];
+        const uint32_t a = bop3<kAnd3>(c[3], c[2], c[1]);
+        t[2] = bop3<kNorAnd>(c[4], a, c[0]);
+        t[3] = ~(c[4] | a);
         // Suffix mismatch vectors (base 0 = A = 00 mismatches where hi|lo,
         // C = 01 where hi|~lo, G = 10 where ~hi|lo, T = 11 where ~(hi&lo)),
         // computed on the scalar unit and copied to VGPRs.
         uint32_t sv[S][4];
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            const uint32_t h = W[P + q], lo = W[L + P + q];
+            const uint32_t h = w[P + q], lo = w[L + P + q];
             sv[q][0] = to_vgpr(h | lo);
             sv[q][1] = to_vgpr(h | ~lo);
             sv[q][2] = to_vgpr(~h | lo);
             sv[q][3] = to_vgpr(~(h & lo));
         }
+        // The thresholds are complete here: pin them before the next loads.
+#pragma unroll
+        for (int k = 0; k <= S; ++k) asm volatile("" : "+v"(t[k]));
+        // Last group: the same words again (read, never used).  The empty asm
+        // keeps the loads below this point.
+        W += gi + 1 < groups ? 2 * L : 0;
+        asm volatile("" : "+s"(W));
+#pragma unroll
+        for (int i = 0; i < 2 * L; ++i) w[i] = W[i];
         // Selection tree down to the next-to-last level.
-        uint32_t u[N1][S];            // level S-1, thresholds k = 0..1 used
+        uint32_t u[N1][2];
         if (S == 2) {
 #pragma unroll
             for (int b1 = 0; b1 < 4; ++b1) {
                 const uint32_t sm = sv[0][b1];
-                u[b1][0] = (sm & t[1]) | (~sm & t[0]);
-                u[b1][1] = (sm & t[2]) | (~sm & t[1]);
+                u[b1][0] = bop3<kMux>(sm, t[1], t[0]);
+                u[b1][1] = bop3<kMux>(sm, t[2], t[1]);
             }
         } else {
 #pragma unroll
@@ -179,12 +207,12 @@ __device__ __forceinline__ typename MaskOf<S>::type scan_group(
                 const uint32_t sm = sv[0][b1];
                 uint32_t v1[3];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) v1[k] = (sm & t[k + 1]) | (~sm & t[k]);
+                for (int k = 0; k < 3; ++k) v1[k] = bop3<kMux>(sm, t[k + 1], t[k]);
 #pragma unroll
                 for (int b2 = 0; b2 < 4; ++b2) {
                     const uint32_t sn = sv[1][b2];
-                    u[b1 * 4 + b2][0] = (sn & v1[1]) | (~sn & v1[0]);
-                    u[b1 * 4 + b2][1] = (sn & v1[2]) | (~sn & v1[1]);
+                    u[b1 * 4 + b2][0] = bop3<kMux>(sn, v1[1], v1[0]);
+                    u[b1 * 4 + b2][1] = bop3<kMux>(sn, v1[2], v1[1]);
                 }
             }
         }
@@ -192,7 +220,8 @@ __device__ __forceinline__ typename MaskOf<S>::type scan_group(
         for (int n = 0; n < N1; ++n) {
             top[n] |= u[n][1];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) found[n * 4 + b] |= u[n][0] & ~sv[S - 1][b];
+            for (int b = 0; b < 4; ++b)
+                found[n * 4 + b] = bop3<kOrAndN>(found[n * 4 + b], u[n][0], sv[S - 1][b]);
         }
     }
     Mask pass = 0;

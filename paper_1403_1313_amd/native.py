@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import threading
 from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -63,7 +64,8 @@ class Stats(ctypes.Structure):
                 ("window_compares", ctypes.c_uint64), ("candidate_slots", ctypes.c_uint64),
                 ("grid", ctypes.c_uint32), ("wg_waves", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("reruns", ctypes.c_uint32),
-                ("variant", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("variant", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("host_prep_ms", ctypes.c_double), ("host_finish_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))
@@ -157,17 +159,37 @@ def _check(status: int, allow=(PMS_OK,)):
     return status
 
 
-def _rows(seqs) -> Tuple[ctypes.Array, list, int, int]:
-    """char* array for n rows (list of str/bytes or an (n, t) uint8 array)."""
+def _rows(seqs) -> Tuple[ctypes.Array, object, int, int]:
+    """char* array for n rows (list of str/bytes or an (n, t) uint8 array).
+
+    For an array the pointers address its rows directly; the second element
+    returned keeps the memory they point into alive."""
     if isinstance(seqs, np.ndarray):
         m = np.ascontiguousarray(seqs, dtype=np.uint8)
-        rows = [m[i].tobytes() for i in range(m.shape[0])]
-    else:
-        rows = [s.encode() if isinstance(s, str) else bytes(s) for s in seqs]
+        if m.ndim != 2:
+            raise ValueError("sequence array must be 2-D (n, t)")
+        n, t = int(m.shape[0]), int(m.shape[1])
+        base = m.ctypes.data
+        arr = (ctypes.c_char_p * max(n, 1))(*[base + i * t for i in range(n)])
+        return arr, m, n, t
+    rows = [s.encode() if isinstance(s, str) else bytes(s) for s in seqs]
     n = len(rows)
     t = len(rows[0]) if rows else 0
     arr = (ctypes.c_char_p * max(n, 1))(*rows) if n else (ctypes.c_char_p * 1)()
     return arr, rows, n, t
+
+
+_tls = threading.local()
+
+
+def _out_buffer(words: int) -> np.ndarray:
+    """Per-thread output scratch reused across calls: results are copied out
+    of it, so a call's buffer only has to outlive the call."""
+    buf = getattr(_tls, "out", None)
+    if buf is None or buf.size < words:
+        buf = np.empty(max(words, 1), dtype=np.uint32)
+        _tls.out = buf
+    return buf
 
 
 def solve_raw(seqs, l: int, d: int, capacity: Optional[int] = None, t: Optional[int] = None):
@@ -176,7 +198,7 @@ def solve_raw(seqs, l: int, d: int, capacity: Optional[int] = None, t: Optional[
     t = t0 if t is None else t
     if capacity is None:
         capacity = 1 << 20
-    out = np.zeros(max(capacity, 1), dtype=np.uint32)
+    out = _out_buffer(capacity)
     cnt = ctypes.c_uint64(capacity)
     st = _lib.pms_solve(arr, n, t, l, d, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
                         if capacity > 0 else None, ctypes.byref(cnt))
@@ -198,11 +220,15 @@ def solve_many(instances: Sequence[Tuple[object, int, int]], capacities=None):
     """pms_solve_many over [(seqs, l, d), ...]: (status, [motifs], [Result])."""
     m = len(instances)
     insts = (Instance * max(m, 1))()
+    caps = [(1 << 16) if capacities is None else int(capacities[i]) for i in range(m)]
+    pool = _out_buffer(sum(max(c, 1) for c in caps))
     keep, outs = [], []
+    off = 0
     for i, (seqs, l, d) in enumerate(instances):
         arr, rows, n, t = _rows(seqs)
-        cap = (1 << 16) if capacities is None else int(capacities[i])
-        out = np.zeros(max(cap, 1), dtype=np.uint32)
+        cap = caps[i]
+        out = pool[off:off + max(cap, 1)]
+        off += max(cap, 1)
         keep.append((arr, rows))
         outs.append(out)
         insts[i].seqs = ctypes.cast(arr, ctypes.POINTER(ctypes.c_char_p))

@@ -38,7 +38,8 @@ def test_struct_layouts_match_header(tmp_path):
         "pms_result": ["status", "count", "latency_ms"],
         "pms_config": ["chunk", "wg_waves", "wgs_per_cu", "tail_split", "variant"],
         "pms_stats": ["kernel_ms", "windows_ms", "seq_visits", "batches", "window_compares",
-                      "candidate_slots", "grid", "wg_waves", "chunk", "reruns", "variant"],
+                      "candidate_slots", "grid", "wg_waves", "chunk", "reruns", "variant",
+                      "host_prep_ms", "host_finish_ms"],
         "pms_dev_instance": ["windows", "out", "out_cap", "n", "nw_stride", "l", "d"],
         "pms_work_item": ["begin", "len", "inst"],
         "pms_dev_state": ["count", "visits", "t_done", "items_left"],
