@@ -109,6 +109,96 @@ __device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
 template <int S> struct MaskOf { typedef uint32_t type; };
 template <> struct MaskOf<3> { typedef uint64_t type; };
 
+// Suffix mismatch vectors of one 32-window group for suffix position q:
+// base 0 = A = 00 mismatches where hi|lo, C = 01 where hi|~lo, G = 10 where
+// ~hi|lo, T = 11 where ~(hi&lo).  Computed on the scalar unit, copied to VGPRs.
+__device__ __forceinline__ void suffix_vectors(uint32_t h, uint32_t lo, uint32_t (&sv)[4]) {
+    sv[0] = to_vgpr(h | lo);
+    sv[1] = to_vgpr(h | ~lo);
+    sv[2] = to_vgpr(~h | lo);
+    sv[3] = to_vgpr(~(h & lo));
+}
+
+// Selection tree over the S suffix positions for one 32-window group, given
+// the thresholds t[k] = [mismatches before the suffix <= d - k], k = 0..S:
+//   U_1[b1][k]    = s_1[b1] ? t[k+1] : t[k]                 k = 0..S-1
+//   U_j[..bj][k]  = s_j[bj] ? U_{j-1}[..][k+1] : U_{j-1}[..][k]
+// U_j[..][k] = [mismatches + s_1 + .. + s_j <= d - k].  The last level is
+// folded into the accumulators: a candidate has a good window where
+//   U_{S-1}[..][1]  |  (~s_S[bS] & U_{S-1}[..][0]).
+template <int S>
+__device__ __forceinline__ void select_accumulate(const uint32_t (&t)[4], const uint32_t (&sv)[S][4],
+                                                  uint32_t (&found)[1 << (2 * S)],
+                                                  uint32_t (&top)[1 << (2 * S - 2)]) {
+    constexpr int N1 = 1 << (2 * S - 2);
+    uint32_t u[N1][2];
+    if constexpr (S == 2) {
+#pragma unroll
+        for (int b1 = 0; b1 < 4; ++b1) {
+            const uint32_t sm = sv[0][b1];
+            u[b1][0] = bop3<kMux>(sm, t[1], t[0]);
+            u[b1][1] = bop3<kMux>(sm, t[2], t[1]);
+        }
+    } else {
+#pragma unroll
+        for (int b1 = 0; b1 < 4; ++b1) {
+            const uint32_t sm = sv[0][b1];
+            uint32_t v1[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v1[k] = bop3<kMux>(sm, t[k + 1], t[k]);
+#pragma unroll
+            for (int b2 = 0; b2 < 4; ++b2) {
+                const uint32_t sn = sv[S - 2][b2];
+                u[b1 * 4 + b2][0] = bop3<kMux>(sn, v1[1], v1[0]);
+                u[b1 * 4 + b2][1] = bop3<kMux>(sn, v1[2], v1[1]);
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+        top[n] |= u[n][1];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            found[n * 4 + b] = bop3<kOrAndN>(found[n * 4 + b], u[n][0], sv[S - 1][b]);
+    }
+}
+
+// Pass mask of a group: candidate c has a window within d.
+//  * 16 candidates: a plain OR of shifted flags.
+//  * 64 candidates: 32 bits at a time as acc = 2 acc + [x_c != 0] from the
+//    highest candidate down, each step one v_cmp (into VCC) and one
+//    v_addc_co_u32 that adds acc to itself with VCC as the carry in.  This
+//    keeps the epilogue to two instructions per candidate and, unlike the
+//    select-and-merge code the compiler forms for the flags, holds few
+//    registers at once, which lets the kernel fit three wavefronts per SIMD.
+template <int S>
+__device__ __forceinline__ typename MaskOf<S>::type group_pass(const uint32_t (&found)[1 << (2 * S)],
+                                                               const uint32_t (&top)[1 << (2 * S - 2)]) {
+    typedef typename MaskOf<S>::type Mask;
+    constexpr int K = 1 << (2 * S);
+    Mask pass = 0;
+    if constexpr (S == 2) {
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+            pass |= static_cast<Mask>((found[c] | top[c >> 2]) != 0u ? 1u : 0u) << c;
+    } else {
+#pragma unroll
+        for (int h = K / 32 - 1; h >= 0; --h) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int c = h * 32 + 31; c >= h * 32; --c) {
+                const uint32_t x = found[c] | top[c >> 2];
+                asm("v_cmp_ne_u32_e32 vcc, 0, %1\n\tv_addc_co_u32_e32 %0, vcc, %0, %0, vcc"
+                    : "+v"(acc)
+                    : "v"(x)
+                    : "vcc");
+            }
+            pass = (pass << 32) | acc;
+        }
+    }
+    return pass;
+}
+
 // One sequence scan for the lane's group of 4^S candidates that share the
 // P = l - S prefix bases `prefix`: returns the mask of candidates with a
 // window within d, restricted to `alive`.  W: the sequence's bit-sliced row
@@ -171,18 +261,9 @@ __device__ __forceinline__ typename MaskOf<S>::type scan_group(
         const uint32_t a = bop3<kAnd3>(c[3], c[2], c[1]);
         t[2] = bop3<kNorAnd>(c[4], a, c[0]);
         t[3] = ~(c[4] | a);
-        // Suffix mismatch vectors (base 0 = A = 00 mismatches where hi|lo,
-        // C = 01 where hi|~lo, G = 10 where ~hi|lo, T = 11 where ~(hi&lo)),
-        // computed on the scalar unit and copied to VGPRs.
         uint32_t sv[S][4];
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const uint32_t h = w[P + q], lo = w[L + P + q];
-            sv[q][0] = to_vgpr(h | lo);
-            sv[q][1] = to_vgpr(h | ~lo);
-            sv[q][2] = to_vgpr(~h | lo);
-            sv[q][3] = to_vgpr(~(h & lo));
-        }
+        for (int q = 0; q < S; ++q) suffix_vectors(w[P + q], w[L + P + q], sv[q]);
         // The thresholds are complete here: pin them before the next loads.
 #pragma unroll
         for (int k = 0; k <= S; ++k) asm volatile("" : "+v"(t[k]));
@@ -192,43 +273,9 @@ __device__ __forceinline__ typename MaskOf<S>::type scan_group(
         asm volatile("" : "+s"(W));
 #pragma unroll
         for (int i = 0; i < 2 * L; ++i) w[i] = W[i];
-        // Selection tree down to the next-to-last level.
-        uint32_t u[N1][2];
-        if (S == 2) {
-#pragma unroll
-            for (int b1 = 0; b1 < 4; ++b1) {
-                const uint32_t sm = sv[0][b1];
-                u[b1][0] = bop3<kMux>(sm, t[1], t[0]);
-                u[b1][1] = bop3<kMux>(sm, t[2], t[1]);
-            }
-        } else {
-#pragma unroll
-            for (int b1 = 0; b1 < 4; ++b1) {
-                const uint32_t sm = sv[0][b1];
-                uint32_t v1[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) v1[k] = bop3<kMux>(sm, t[k + 1], t[k]);
-#pragma unroll
-                for (int b2 = 0; b2 < 4; ++b2) {
-                    const uint32_t sn = sv[1][b2];
-                    u[b1 * 4 + b2][0] = bop3<kMux>(sn, v1[1], v1[0]);
-                    u[b1 * 4 + b2][1] = bop3<kMux>(sn, v1[2], v1[1]);
-                }
-            }
-        }
-#pragma unroll
-        for (int n = 0; n < N1; ++n) {
-            top[n] |= u[n][1];
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                found[n * 4 + b] = bop3<kOrAndN>(found[n * 4 + b], u[n][0], sv[S - 1][b]);
-        }
+        select_accumulate<S>(t, sv, found, top);
     }
-    Mask pass = 0;
-#pragma unroll
-    for (int c = 0; c < K; ++c)
-        pass |= static_cast<Mask>((found[c] | top[c >> 2]) != 0u ? 1u : 0u) << c;
-    return pass & alive;
+    return group_pass<S>(found, top) & alive;
 }
 
 // Dispatch on the number of prefix positions (wave-uniform).
@@ -473,7 +520,9 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
 
 }  // namespace
 
-extern "C" __global__ void __launch_bounds__(1024)
+// At most 5 wavefronts per SIMD: with the register budget that leaves, the
+// prefix masks stay in registers instead of being rebuilt every iteration.
+extern "C" __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(1, 5)))
 pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
                         const pms_work_item* __restrict__ work, uint32_t n_work,
                         pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
