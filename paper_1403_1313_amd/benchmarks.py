@@ -137,13 +137,16 @@ def bench_serving(args):
     from . import native as nat
     from .serve import Server
 
-    rates = [float(r) for r in os.environ.get("PMS_SERVE_RATES", "10,20,40").split(",")]
-    count = int(os.environ.get("PMS_SERVE_COUNT", "60"))
+    rates = [float(r) for r in os.environ.get("PMS_SERVE_RATES", "20,200,1000").split(",")]
+    fixed = os.environ.get("PMS_SERVE_COUNT")
+    step_ms = float(os.environ.get("PMS_SERVE_STEP_MS", "2.0"))
     out = []
     for rate in rates:
+        # about a second of arrivals, at least 60 and at most 300 requests
+        count = int(fixed) if fixed else int(min(300, max(60, rate)))
         stream = fmgen.serving_stream(count, rate)
         reqs = [(t_arr, spec.make()) for t_arr, spec in stream]
-        with Server(mem_budget=256 << 20) as srv:
+        with Server(mem_budget=256 << 20, step_ms=step_ms) as srv:
             # warm up the kernels and allocator
             srv.submit(reqs[0][1].seqs, reqs[0][1].l, reqs[0][1].d).result()
             t0 = time.perf_counter()
@@ -156,6 +159,7 @@ def bench_serving(args):
             results = [f.result() for f in futs]
             span = max(r.finished for r in results) - t0
             stats = dict(srv.stats)
+            stats["compares_per_s_estimate"] = srv.rate
         lat = [r.latency_s * 1e3 for r in results]
         # the same arrivals served one instance per launch, first come first served
         t1 = time.perf_counter()
@@ -176,12 +180,13 @@ def bench_serving(args):
     best = max(out, key=lambda r: r["solves_per_s"])
     line = {
         "metric": "served solves/s", "value": best["solves_per_s"], "unit": "solves/s",
-        "n_gpus": 1, "steps": count, "warmup": 1, "ms_per_step": 1e3 / best["solves_per_s"],
+        "n_gpus": 1, "steps": best["requests"], "warmup": 1, "ms_per_step": 1e3 / best["solves_per_s"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": "Poisson stream of seeded FM solve requests, (l,d) over "
                                "(9,2),(11,3),(13,4),(15,4) weighted 4:3:2:1, n in [10,30], "
-                               "t in [300,1000], master seed 1313", "rates": rates},
+                               "t in [300,1000], master seed 1313", "rates": rates,
+                   "requests": [r["requests"] for r in out], "step_ms": step_ms},
         "sweep": out,
     }
     print(json.dumps(line), flush=True)

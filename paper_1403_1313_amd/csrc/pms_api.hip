@@ -19,6 +19,7 @@
 #include <mutex>
 #include <numeric>
 #include <chrono>
+#include <map>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -154,11 +155,22 @@ int validate_rows(const char* const* seqs, int32_t n, int32_t t) {
     for (int32_t i = 0; i < n; ++i) {
         const char* r = seqs[i];
         if (!r) return fail(PMS_ERR_INVALID, "seqs[" + std::to_string(i) + "] is NULL");
+        // Branch-free pass over the row (the compiler vectorises it); the
+        // position is looked up only for the error message.
+        const unsigned char* u = reinterpret_cast<const unsigned char*>(r);
+        unsigned bad = 0;
         for (int32_t j = 0; j < t; ++j) {
-            const unsigned c = static_cast<unsigned char>(r[j]) | 0x20u;
-            if (c != 'a' && c != 'c' && c != 'g' && c != 't')
-                return fail(PMS_ERR_INVALID, "byte " + std::to_string(j) + " of sequence " +
-                                                 std::to_string(i) + " is not A/C/G/T");
+            const unsigned c = u[j] | 0x20u;
+            bad |= static_cast<unsigned>(c != 'a') & static_cast<unsigned>(c != 'c') &
+                   static_cast<unsigned>(c != 'g') & static_cast<unsigned>(c != 't');
+        }
+        if (bad) {
+            for (int32_t j = 0; j < t; ++j) {
+                const unsigned c = u[j] | 0x20u;
+                if (c != 'a' && c != 'c' && c != 'g' && c != 't')
+                    return fail(PMS_ERR_INVALID, "byte " + std::to_string(j) + " of sequence " +
+                                                     std::to_string(i) + " is not A/C/G/T");
+            }
         }
     }
     return PMS_OK;
@@ -231,6 +243,13 @@ struct Batch {
            meta_bytes = 0;
 };
 
+// Shape of one search launch.
+struct Shape2 {
+    uint32_t grid = 0, waves = 0;
+    uint32_t q_words = 0;          // per-lane kernel: LDS queue words per wavefront
+    pms::GroupQueues gq{0, nullptr, 0};
+};
+
 struct Ctx {
     std::mutex mu;
     bool ready = false;
@@ -269,6 +288,8 @@ struct Ctx {
     const void* dv_uploaded = nullptr;
     // entry time of the current host-level call (host_prep_ms)
     std::chrono::steady_clock::time_point t_call;
+    // launch shapes by (variant, max_n, wg_waves, wgs_per_cu)
+    std::map<uint64_t, Shape2> shapes;
 };
 
 Ctx g_ctx;
@@ -306,19 +327,33 @@ int init_ctx(Ctx& c) {
     return PMS_OK;
 }
 
-// Workgroup shape and grid for a search launch.
-// Shape of one search launch.
-struct Shape2 {
-    uint32_t grid = 0, waves = 0;
-    uint32_t q_words = 0;          // per-lane kernel: LDS queue words per wavefront
-    pms::GroupQueues gq{0, nullptr, 0};
-};
+int query_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, Shape2* out);
 
 // Workgroup shape, grid and queue placement for a search launch.  The
 // grouped kernels keep as many stage queues in LDS as the occupancy their
 // registers allow leaves room for, and the rest in `ws` (grown as needed).
 int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, DevBuf& ws,
                  Shape2* out) {
+    // The kernel attribute and occupancy queries depend only on these four
+    // values; their answers are kept for later launches.
+    const uint64_t key = (static_cast<uint64_t>(variant) << 48) |
+                         (static_cast<uint64_t>(max_n) << 32) |
+                         (static_cast<uint64_t>(cfg.wg_waves) << 16) | cfg.wgs_per_cu;
+    auto hit = c.shapes.find(key);
+    if (hit == c.shapes.end()) {
+        Shape2 sh;
+        PMS_TRY(query_shape(c, cfg, max_n, variant, &sh));
+        hit = c.shapes.emplace(key, sh).first;
+    }
+    *out = hit->second;
+    if (out->gq.gq_words) {
+        PMS_TRY(ws.ensure(static_cast<size_t>(out->grid) * out->waves * out->gq.gq_words * 4));
+        out->gq.gq = ws.as<uint32_t>();
+    }
+    return PMS_OK;
+}
+
+int query_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, Shape2* out) {
     const uint32_t stages = static_cast<uint32_t>(max_n > 1 ? max_n - 1 : 0);
     const void* fn = variant == PMS_VARIANT_LANE
                          ? pms::search_kernel_symbol()
@@ -352,10 +387,6 @@ int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant,
     out->waves = w;
     out->q_words = variant == PMS_VARIANT_LANE ? pms::queue_words(max_n, variant) : 0;
     out->gq = {lds_stages, nullptr, gq_words};
-    if (gq_words) {
-        PMS_TRY(ws.ensure(static_cast<size_t>(out->grid) * w * gq_words * 4));
-        out->gq.gq = ws.as<uint32_t>();
-    }
     return PMS_OK;
 }
 

@@ -101,7 +101,11 @@ class _StepBuf:
         self.d_work = torch.zeros(max_items * 16, dtype=torch.uint8, device=dev)
         self.d_ctr = torch.zeros(4, dtype=torch.int64, device=dev)
         self.h_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8).pin_memory()
-        self.event = None
+        self.event = None           # end of the search launch (timed)
+        self.done = None            # state snapshot copied to the host
+        self.start = None
+        self.compares = 0.0         # estimated window compares of the step
+        self.budget = 0.0           # the step's budget when it was built
         self.reqs: List[_Req] = []
         self.items_per_req: Dict[int, int] = {}
 
@@ -109,8 +113,8 @@ class _StepBuf:
 class Server:
     """Continuous-batching server.  ``submit`` returns a Future of ``Result``."""
 
-    def __init__(self, mem_budget: int = 256 << 20, step_ms: float = 3.0,
-                 max_inflight: int = 2, compares_per_s: float = 7e13,
+    def __init__(self, mem_budget: int = 256 << 20, step_ms: float = 2.0,
+                 max_inflight: int = 2, compares_per_s: float = 2.5e14,
                  device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
                  items_per_step: int = 8192):
         import torch
@@ -119,7 +123,11 @@ class Server:
         torch.cuda.set_device(self.dev)
         self.stream = torch.cuda.Stream(self.dev)
         self.mem_budget = int(mem_budget)
-        self.step_compares = step_ms * 1e-3 * compares_per_s
+        # Steps are sized in estimated window compares; the rate starts at
+        # compares_per_s and follows the measured device time of each step.
+        self.step_s = step_ms * 1e-3
+        self.rate = float(compares_per_s)
+        self.step_compares = self.step_s * self.rate
         self.items_per_step = int(items_per_step)
         self.copy_stream = torch.cuda.Stream(self.dev)
         self.max_inflight = int(max_inflight)
@@ -254,7 +262,9 @@ class Server:
         live = [r for r in self.active if r.cursor < r.total]
         if not live:
             return 0
+        buf.compares = 0.0
         budget = self.step_compares
+        buf.budget = budget
         oldest = min(live, key=lambda r: r.arrival)
         order = sorted(live, key=lambda r: (r.total - r.cursor) * r.cost_per_cand)
         shares = {oldest.rid: 0.5 * budget}
@@ -290,6 +300,7 @@ class Server:
             rec["inst"] = r.slot
             parts.append(rec)
             r.cursor += int(lens.sum())
+            buf.compares += float(lens.sum()) * r.cost_per_cand
             per_req[r.slot] = k
             used += k
         if not parts:
@@ -316,12 +327,16 @@ class Server:
         with torch.cuda.stream(self.stream):
             buf.d_work[:n_items * 16].copy_(buf.h_work[:n_items * 16], non_blocking=True)
             buf.d_ctr.zero_()
+            buf.start = torch.cuda.Event(enable_timing=True)
+            buf.start.record(self.stream)
         nat.step_launch(self.d_insts, MAX_SLOTS, max_n, buf.d_work, n_items, self.d_state,
                         buf.d_ctr, config=cfg, stream=self.stream)
         with torch.cuda.stream(self.stream):
-            buf.h_state.copy_(self.d_state, non_blocking=True)
-            buf.event = torch.cuda.Event()
+            buf.event = torch.cuda.Event(enable_timing=True)
             buf.event.record(self.stream)
+            buf.h_state.copy_(self.d_state, non_blocking=True)
+            buf.done = torch.cuda.Event()
+            buf.done.record(self.stream)
         for r in buf.reqs:
             r.inflight += 1
             r.steps += 1
@@ -331,7 +346,15 @@ class Server:
         return True
 
     def _retire(self, buf: _StepBuf):
-        buf.event.synchronize()
+        buf.done.synchronize()
+        ms = buf.start.elapsed_time(buf.event)
+        # Only steps that filled at least half their budget say how fast the
+        # device is; a step that held all the work there was is dominated by
+        # fixed costs and would drag the estimate (and the steps) down.
+        if ms > 0.05 and buf.compares >= 0.5 * buf.budget:
+            measured = buf.compares / (ms * 1e-3)
+            self.rate = min(max(0.7 * self.rate + 0.3 * measured, 1e11), 1e16)
+            self.step_compares = self.step_s * self.rate
         states = np.frombuffer(buf.h_state.numpy().tobytes(), dtype=[
             ("count", "<u8"), ("visits", "<u8"), ("t_done", "<u8"), ("items_left", "<u4"),
             ("reserved", "<u4")])
@@ -394,7 +417,7 @@ class Server:
                     launched = True
                 if self.inflight:
                     head = self.inflight[0]
-                    if head.event.query() or not launched:
+                    if head.done.query() or not launched:
                         self.inflight.popleft()
                         self._retire(head)
         except BaseException as e:  # noqa: BLE001 - every request learns of the failure

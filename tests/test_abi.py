@@ -131,6 +131,26 @@ def test_invalid_pointers_and_bytes():
         assert "not A/C/G/T" in nat.last_error()
 
 
+def test_byte_classification_every_value():
+    """Every byte value at an odd position of a 70-byte row: only A/C/G/T in
+    either case pass validation, and a rejection names the position."""
+    lib = nat.lib()
+    out = np.zeros(4, dtype=np.uint32)
+    optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    base = bytearray(b"ACGT" * 17 + b"AC")
+    for v in range(256):
+        row = bytearray(base)
+        row[37] = v
+        arr = (ctypes.c_char_p * 1)(bytes(row))
+        cnt = ctypes.c_uint64(0)
+        st = lib.pms_solve(arr, 1, 70, 4, 1, optr, ctypes.byref(cnt))
+        if bytes([v]) in b"ACGTacgt":
+            assert st in (nat.PMS_OK, nat.PMS_ERR_DEVICE), v
+        else:
+            assert st == nat.PMS_ERR_INVALID, v
+            assert "byte 37 of sequence 0" in nat.last_error(), v
+
+
 def test_solve_many_rejects_bad_batches():
     lib = nat.lib()
     res = (nat.Result * 1)()
