@@ -23,6 +23,8 @@ from . import build as _build
 
 BRUTE = 0
 SKIP = 1
+MASK_N = 1   # oracle_solve_ex flags
+BOTH = 2
 _MODES = {"brute": BRUTE, "skip": SKIP}
 
 
@@ -54,6 +56,12 @@ class OracleLib:
             ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
             ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
         lib.oracle_candidate_distances.restype = ctypes.c_int
+        lib.oracle_solve_ex.argtypes = [
+            ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+            ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint64,
+            u64p, u64p]
+        lib.oracle_solve_ex.restype = ctypes.c_int
         self.lib = lib
         self.path = path
 
@@ -82,6 +90,37 @@ class OracleLib:
             ctypes.byref(count), ctypes.byref(visits))
         if rc != 0:
             raise ValueError(f"oracle_solve failed with code {rc}")
+        if count.value > cap:
+            raise OverflowError(f"{count.value} motifs exceed cap {cap}")
+        res = out[:count.value].copy()
+        return (res, int(visits.value)) if return_visits else res
+
+    def solve_ex(self, rows, l: int, d: int, mask_n: bool = False, both: bool = False,
+                 mode: str = "brute", threads: Optional[int] = None,
+                 k_range: Optional[Tuple[int, int]] = None, cap: Optional[int] = None,
+                 return_visits: bool = False):
+        """``solve`` for rows of their own lengths, with N masking and/or both
+        strands (``oracle_solve_ex``).  ``rows``: list of str/bytes."""
+        data = [r.encode() if isinstance(r, str) else bytes(r) for r in rows]
+        n = len(data)
+        arr = (ctypes.c_char_p * max(n, 1))(*data)
+        lens = (ctypes.c_int * max(n, 1))(*[len(r) for r in data])
+        total = 1 << (2 * l)
+        k0, k1 = (0, total) if k_range is None else (int(k_range[0]), int(k_range[1]))
+        if threads is None:
+            threads = os.cpu_count() or 1
+        if cap is None:
+            cap = min(max(k1 - k0, 0), 1 << 24)
+        out = np.empty(max(cap, 1), dtype=np.uint32)
+        count = ctypes.c_uint64(0)
+        visits = ctypes.c_uint64(0)
+        flags = (MASK_N if mask_n else 0) | (BOTH if both else 0)
+        rc = self.lib.oracle_solve_ex(
+            arr, lens, n, l, d, flags, k0, k1, _MODES[mode], int(threads),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), cap,
+            ctypes.byref(count), ctypes.byref(visits))
+        if rc != 0:
+            raise ValueError(f"oracle_solve_ex failed with code {rc}")
         if count.value > cap:
             raise OverflowError(f"{count.value} motifs exceed cap {cap}")
         res = out[:count.value].copy()
@@ -117,6 +156,10 @@ def default() -> OracleLib:
 
 def solve(seqs, l: int, d: int, **kw):
     return default().solve(seqs, l, d, **kw)
+
+
+def solve_ex(rows, l: int, d: int, **kw):
+    return default().solve_ex(rows, l, d, **kw)
 
 
 def candidate_distances(seqs, l: int, k: int) -> np.ndarray:

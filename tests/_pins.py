@@ -300,3 +300,121 @@ def pin_ranges_and_distances(orc, seed: int = 13) -> None:
 
 ALL_PINS = [pin_definition_tiny, pin_skip_visits, pin_closed_forms, pin_edges,
             pin_ball_intersection, pin_invariants, pin_ranges_and_distances]
+
+
+# ---------------------------------------------------------------------------
+# Rows of their own lengths, N masking and both strands (the oracle's
+# ``solve_ex``; the reading of Section VI's real-sequence future work)
+# ---------------------------------------------------------------------------
+RC = {"A": "T", "C": "G", "G": "C", "T": "A"}
+
+
+def revcomp(s: str) -> str:
+    return "".join(RC[c] for c in reversed(s.upper()))
+
+
+def definition_window_set(row: str, l: int, mask_n: bool, both: bool) -> List[str]:
+    """W_i spelled out: every length-l substring (none holding N when masking),
+    plus, for both strands, the reverse complement of each."""
+    row = row.upper()
+    fwd = [row[j:j + l] for j in range(len(row) - l + 1)]
+    if mask_n:
+        fwd = [w for w in fwd if "N" not in w]
+    return fwd + ([revcomp(w) for w in fwd] if both else [])
+
+
+def definition_motifs_ex(rows: Sequence[str], l: int, d: int, mask_n: bool, both: bool) -> List[int]:
+    sets = [definition_window_set(r, l, mask_n, both) for r in rows]
+    out = []
+    for k, x in enumerate(itertools.product(BASES, repeat=l)):
+        if all(any(sum(a != b for a, b in zip(x, w)) <= d for w in ws) for ws in sets):
+            out.append(k)
+    return out
+
+
+def random_rows_ex(rng, n: int, l: int, t_max: int, n_rate: float) -> List[str]:
+    """Rows of lengths in [l, t_max] over ACGT (either case) with N at n_rate."""
+    rows = []
+    for _ in range(n):
+        t = int(rng.integers(l, t_max + 1))
+        codes = rng.integers(0, 4, t)
+        row = "".join("ACGT"[c] if rng.random() > 0.3 else "acgt"[c] for c in codes)
+        row = "".join("N" if rng.random() < n_rate else ch for ch in row)
+        rows.append(row)
+    return rows
+
+
+def number_of(s: str) -> int:
+    return int("".join(str("ACGT".index(c)) for c in s.upper()), 4) if s else 0
+
+
+def pin_ex_definition_tiny(orc, cases: int = 80, seed: int = 17) -> None:
+    """Exhaustive enumeration against the spelled-out window sets: ragged
+    lengths, N masking and both strands, every d."""
+    rng = np.random.default_rng(seed)
+    for case in range(cases):
+        l = int(rng.integers(1, 5))
+        n = int(rng.integers(1, 5))
+        mask_n, both = bool(case & 1), bool(case & 2)
+        rows = random_rows_ex(rng, n, l, l + 9, 0.12 if mask_n else 0.0)
+        for d in range(0, l + 1):
+            want = definition_motifs_ex(rows, l, d, mask_n, both)
+            for mode in ("brute", "skip"):
+                got = orc.solve_ex(rows, l, d, mask_n=mask_n, both=both, mode=mode,
+                                   threads=int(rng.integers(1, 4)))
+                assert list(got) == want, (mode, l, d, mask_n, both, rows)
+
+
+def pin_ex_identities(orc, seed: int = 19) -> None:
+    """Identities between the options, each side computed by a different route.
+
+    * both strands on S = N masking on s + "N" + revcomp(s) (a window across
+      the junction holds the N);
+    * ragged lengths = N masking on rows padded with N to one length;
+    * no options, equal lengths = the plain oracle;
+    * with both strands M is closed under reverse complement.
+    """
+    rng = np.random.default_rng(seed)
+    for _ in range(12):
+        l = int(rng.integers(3, 7))
+        d = int(rng.integers(0, 3))
+        rows = random_rows_ex(rng, int(rng.integers(2, 5)), l, 40, 0.0)
+        both = orc.solve_ex(rows, l, d, both=True)
+        glued = [r + "N" + revcomp(r) for r in rows]
+        assert list(both) == list(orc.solve_ex(glued, l, d, mask_n=True)), (l, d, rows)
+        rc_of = {number_of(revcomp(number_to_string(int(k), l))) for k in both}
+        assert rc_of == {int(k) for k in both}, (l, d, rows)
+        t_max = max(len(r) for r in rows)
+        padded = [r + "N" * (t_max - len(r)) for r in rows]
+        assert list(orc.solve_ex(rows, l, d)) == list(orc.solve_ex(padded, l, d, mask_n=True))
+        eq = [r[:l + 20].ljust(l + 20, "A") for r in rows]
+        mat = np.frombuffer("".join(eq).encode(), dtype=np.uint8).reshape(len(eq), -1)
+        assert list(orc.solve_ex(eq, l, d)) == list(orc.solve(mat, l, d))
+
+
+def number_to_string(k: int, l: int) -> str:
+    return "".join(BASES[(k >> (2 * (l - 1 - p))) & 3] for p in range(l))
+
+
+def pin_ex_closed_forms(orc) -> None:
+    """A sequence whose only N-free window is w keeps exactly the ball around
+    w (and around revcomp(w) as well, with both strands); a sequence with no
+    N-free window empties M; N itself is refused without masking."""
+    rng = np.random.default_rng(23)
+    for l in (2, 4, 6):
+        w = "".join(rng.choice(list(BASES), l))
+        row = "NN" + w + "N" + "ACGT"[: max(0, l - 2)]
+        for d in range(0, l + 1):
+            assert orc.solve_ex([row], l, d, mask_n=True).size == ball_size(l, d), (l, d)
+        if w != revcomp(w):
+            ball_w = set(definition_motifs_ex([w], l, 1, False, False))
+            ball_rc = set(definition_motifs_ex([revcomp(w)], l, 1, False, False))
+            got = set(int(k) for k in orc.solve_ex([row], l, 1, mask_n=True, both=True))
+            assert got == ball_w | ball_rc, (l, w)
+    assert orc.solve_ex(["ACGTACGT", "ACNNNNGT"], 3, 3, mask_n=True).size == 0
+    try:
+        orc.solve_ex(["ACGTNACG"], 3, 1)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("N accepted without masking")

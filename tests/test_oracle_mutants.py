@@ -30,6 +30,27 @@ MUTANTS = {
                             "}\n            if (m <= d && job->mode == ORACLE_SKIP) { break;"),
 }
 
+# Mistakes in the extended-input path (oracle_solve_ex).
+EX_MUTANTS = {
+    "ex_mask_keeps_n": ("if (has_n) continue;", ""),
+    "ex_no_complement": ("= complement(w[(size_t)q * l + l - 1 - p]);",
+                         "= w[(size_t)q * l + l - 1 - p];"),
+    "ex_rc_not_reversed": ("complement(w[(size_t)q * l + l - 1 - p])",
+                           "complement(w[(size_t)q * l + p])"),
+    "ex_drops_last_start": ("const int nstarts = t - l + 1;", "const int nstarts = t - l;"),
+    "ex_mask_misses_last_base": ("for (int p = 0; p < l; ++p) has_n |= up[j + p] == 'N';",
+                                 "for (int p = 0; p < l - 1; ++p) has_n |= up[j + p] == 'N';"),
+    "ex_strict_threshold": ("if (d < m) {", "if (d <= m) {"),
+    "ex_bad_complement": ("case 'C': return 'G';", "case 'C': return 'C';"),
+    "ex_rc_skips_first": ("for (int q = 0; q < fwd; ++q) {", "for (int q = 1; q < fwd; ++q) {"),
+}
+
+EX_PINS = [
+    lambda o: _pins.pin_ex_definition_tiny(o, cases=40),
+    _pins.pin_ex_identities,
+    _pins.pin_ex_closed_forms,
+]
+
 QUICK_PINS = [
     lambda o: _pins.pin_definition_tiny(o, cases=40),
     lambda o: _pins.pin_skip_visits(o, cases=15),
@@ -74,3 +95,22 @@ def test_unmutated_copy_passes(tmp_path, src):
     orc = oracle.OracleLib(lib)
     for pin in QUICK_PINS:
         pin(orc)
+
+
+@pytest.mark.parametrize("name", sorted(EX_MUTANTS))
+def test_ex_mutant_is_caught(tmp_path, src, name):
+    old, new = EX_MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    lib = str(tmp_path / f"lib_{name}.so")
+    obuild.build(str(path), lib)
+    orc = oracle.OracleLib(lib)
+    caught = []
+    for pin in EX_PINS:
+        try:
+            pin(orc)
+        except (AssertionError, ValueError, OverflowError) as e:  # noqa: PERF203
+            caught.append(repr(e)[:80])
+            break
+    assert caught, f"mutant {name} passed every pin"
