@@ -71,6 +71,19 @@ enum pms_status {
 int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t d,
               uint32_t* out_motifs, uint64_t* out_count);
 
+/*
+ * pms_solve_ex -- pms_solve for sequences of their own lengths, with options
+ * (pms_input_flag): seqs[i] has lengths[i] bytes, l <= lengths[i] <=
+ * PMS_MAX_T.  The window set of sequence i is every length-l substring (none
+ * holding N under PMS_INPUT_MASK_N), plus their reverse complements under
+ * PMS_INPUT_BOTH_STRANDS; M is defined over these sets as for pms_solve.
+ * A sequence with no window leaves M empty (PMS_OK, |M| = 0, no device
+ * work).  Same output, capacity and error semantics as pms_solve; lengths
+ * NULL or an unknown flag is PMS_ERR_INVALID.
+ */
+int pms_solve_ex(const char* const* seqs, int32_t n, const int32_t* lengths, int32_t l,
+                 int32_t d, uint32_t flags, uint32_t* out_motifs, uint64_t* out_count);
+
 /* One instance of a batched solve (host buffers). */
 typedef struct {
     const char* const* seqs; /* n pointers to >= t bytes each, as for pms_solve */
@@ -128,6 +141,18 @@ enum pms_layout {
     PMS_LAYOUT_PLANES = 0,    /* [row][window] uint32: high plane << 16 | low plane */
     PMS_LAYOUT_BITSLICED = 1  /* [row][group of 32 windows][2l] uint32: word p has bit j =
                                  high bit of base p of window 32g+j, word l+p the low bit */
+};
+
+/* Input options of pms_solve_ex (bit flags).  The reading of the
+ * real-sequence future work of Section VI:
+ *   PMS_INPUT_MASK_N        bytes N/n are allowed; a window holding one is
+ *                           not a window of its sequence.
+ *   PMS_INPUT_BOTH_STRANDS  a sequence's windows also include the reverse
+ *                           complement of each of its windows (read
+ *                           backwards, A<->T, C<->G). */
+enum pms_input_flag {
+    PMS_INPUT_MASK_N = 1,
+    PMS_INPUT_BOTH_STRANDS = 2
 };
 
 /* Shape of the persistent search launch.  Zero fields mean "default". */

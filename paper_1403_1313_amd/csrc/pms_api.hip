@@ -139,7 +139,15 @@ pms_config resolve(const pms_config* c, const pms_config& cur) {
 // Per-instance planning.
 // ---------------------------------------------------------------------------
 struct Shape {
-    int32_t n, t, l, d;
+    int32_t n, t, l, d;              // t: the longest row
+    const int32_t* lens = nullptr;   // per-row lengths (pms_solve_ex); null: every row has t
+    uint32_t flags = 0;              // pms_input_flag bits
+    int32_t row_len(int32_t r) const { return lens ? lens[r] : t; }
+    // Window slots of a row in the table: the longest row's windows, twice
+    // with both strands.
+    int32_t slots() const { return (t - l + 1) * ((flags & PMS_INPUT_BOTH_STRANDS) ? 2 : 1); }
+    // The row length whose t-l+1 windows fill those slots (for window_stride).
+    int32_t table_t() const { return slots() + l - 1; }
 };
 
 int validate_shape(int32_t n, int32_t t, int32_t l, int32_t d) {
@@ -176,6 +184,33 @@ int validate_rows(const char* const* seqs, int32_t n, int32_t t) {
     return PMS_OK;
 }
 
+// Rows of their own lengths under pms_input_flag options.  N/n is a valid
+// byte only with PMS_INPUT_MASK_N.  *empty is set when some row has no window
+// free of N (its instance then has no motifs).
+int validate_rows_ex(const char* const* seqs, int32_t n, const int32_t* lens, int32_t l,
+                     uint32_t flags, bool* empty) {
+    if (!seqs) return fail(PMS_ERR_INVALID, "seqs is NULL");
+    const bool mask_n = (flags & PMS_INPUT_MASK_N) != 0;
+    *empty = false;
+    for (int32_t i = 0; i < n; ++i) {
+        const unsigned char* u = reinterpret_cast<const unsigned char*>(seqs[i]);
+        if (!u) return fail(PMS_ERR_INVALID, "seqs[" + std::to_string(i) + "] is NULL");
+        int32_t run = 0, best = 0;  // longest stretch without N
+        for (int32_t j = 0; j < lens[i]; ++j) {
+            const unsigned c = u[j] | 0x20u;
+            const bool base = c == 'a' || c == 'c' || c == 'g' || c == 't';
+            if (!base && !(mask_n && c == 'n'))
+                return fail(PMS_ERR_INVALID, "byte " + std::to_string(j) + " of sequence " +
+                                                 std::to_string(i) + " is not A/C/G/T" +
+                                                 (mask_n ? "/N" : ""));
+            run = base ? run + 1 : 0;
+            best = std::max(best, run);
+        }
+        if (best < l) *empty = true;
+    }
+    return PMS_OK;
+}
+
 int32_t window_stride(int32_t t, int32_t l, int32_t layout) {
     if (l < 1 || t < l) return 0;
     const size_t nw = static_cast<size_t>(t - l + 1);
@@ -200,7 +235,7 @@ Estimate estimate(const Shape& s) {
     }
     const double cands = std::ldexp(1.0, 2 * s.l);
     const double p = ball / cands;
-    const double nw = s.t - s.l + 1;
+    const double nw = s.slots();
     const double ps = 1.0 - std::pow(1.0 - p, nw);
     double ev = 0, pk = 1;
     for (int k = 0; k < s.n; ++k) {
@@ -451,21 +486,24 @@ void plan_batch(Batch& b, const pms_config& cfg, uint64_t target_items) {
     std::vector<double> cost(m);
     for (size_t i = 0; i < m; ++i) {
         const Shape& s = b.shape[i];
-        const int32_t stride = window_stride(s.t, s.l, layout);
+        const int32_t stride = window_stride(s.table_t(), s.l, layout);
         b.raw_off[i] = b.raw_bytes;
         b.win_off[i] = b.win_words;
         b.out_off[i] = b.out_words;
         if (b.out_cap[i] == 0) b.out_cap[i] = output_capacity(s);
-        for (int32_t r = 0; r < s.n; ++r)
-            b.jobs.push_back({b.raw_off[i] + static_cast<size_t>(r) * s.t,
-                              b.win_off[i] + static_cast<size_t>(r) * stride, s.t, s.l, stride,
-                              static_cast<int32_t>(i), layout, 0});
-        b.raw_bytes += align_up(static_cast<size_t>(s.n) * s.t, 256);
+        size_t row_off = 0;  // rows are packed back to back
+        for (int32_t r = 0; r < s.n; ++r) {
+            b.jobs.push_back({b.raw_off[i] + row_off, b.win_off[i] + static_cast<size_t>(r) * stride,
+                              s.row_len(r), s.l, stride, static_cast<int32_t>(i), layout,
+                              static_cast<int32_t>(s.flags)});
+            row_off += static_cast<size_t>(s.row_len(r));
+        }
+        b.raw_bytes += align_up(row_off, 256);
         b.win_words += static_cast<size_t>(s.n) * stride;
         b.out_words += align_up(b.out_cap[i], 64);
         b.max_n = std::max(b.max_n, s.n);
         b.max_t = std::max(b.max_t, s.t);
-        cost[i] = std::ldexp(1.0, 2 * s.l) * (s.t - s.l + 1) * estimate(s).visits;
+        cost[i] = std::ldexp(1.0, 2 * s.l) * s.slots() * estimate(s).visits;
     }
     std::vector<int> order(m);
     std::iota(order.begin(), order.end(), 0);
@@ -500,7 +538,10 @@ int stage_batch(Ctx& c, Batch& b) {
     for (size_t i = 0; i < m; ++i) {
         const Shape& s = b.shape[i];
         char* dst = c.h_raw.as<char>(b.raw_off[i]);
-        for (int32_t r = 0; r < s.n; ++r) memcpy(dst + static_cast<size_t>(r) * s.t, b.rows[i][r], s.t);
+        for (int32_t r = 0; r < s.n; ++r) {
+            memcpy(dst, b.rows[i][r], static_cast<size_t>(s.row_len(r)));
+            dst += s.row_len(r);
+        }
     }
     memset(c.h_meta.p, 0, b.meta_bytes);
     pms_dev_instance* insts = c.h_meta.as<pms_dev_instance>(b.off_insts);
@@ -512,7 +553,7 @@ int stage_batch(Ctx& c, Batch& b) {
         insts[i].out_cap = b.out_cap[i];
         insts[i].n = s.n;
         insts[i].nw_stride = window_stride(
-            s.t, s.l, b.variant == PMS_VARIANT_LANE ? PMS_LAYOUT_PLANES : PMS_LAYOUT_BITSLICED);
+            s.table_t(), s.l, b.variant == PMS_VARIANT_LANE ? PMS_LAYOUT_PLANES : PMS_LAYOUT_BITSLICED);
         insts[i].l = s.l;
         insts[i].d = s.d;
         state[i].items_left = b.items_per_inst[i];
@@ -651,7 +692,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     for (size_t i = 0; i < m; ++i) {
         counts[i] = st[i].count;
         visits += st[i].visits;
-        wcmp += st[i].visits * static_cast<uint64_t>(shapes[i].t - shapes[i].l + 1);
+        wcmp += st[i].visits * static_cast<uint64_t>(shapes[i].slots());
         latency[i] = st[i].t_done > ctr->t_start ? (st[i].t_done - ctr->t_start) * 1e-5 : 0.0;
         if (bad[i]) status[i] = fail(PMS_ERR_INVALID, "a byte is not A/C/G/T");
         if (st[i].items_left != 0 || ctr->error)
@@ -884,6 +925,45 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t 
     std::vector<double> lat;
     PMS_TRY(solve_instances(g_ctx, {Shape{n, t, l, d}}, {seqs}, {out_motifs}, {cap}, status,
                             counts, lat, false));
+    *out_count = counts[0];
+    return status[0];
+}
+
+int pms_solve_ex(const char* const* seqs, int32_t n, const int32_t* lengths, int32_t l,
+                 int32_t d, uint32_t flags, uint32_t* out_motifs, uint64_t* out_count) {
+    const auto t_call = std::chrono::steady_clock::now();
+    g_last_error.clear();
+    if (!out_count) return fail(PMS_ERR_INVALID, "out_count is NULL");
+    const uint64_t cap = *out_count;
+    *out_count = 0;
+    if (!lengths) return fail(PMS_ERR_INVALID, "lengths is NULL");
+    if (flags & ~static_cast<uint32_t>(PMS_INPUT_MASK_N | PMS_INPUT_BOTH_STRANDS))
+        return fail(PMS_ERR_INVALID, "unknown input flag");
+    if (n < 1 || n > PMS_MAX_N) return fail(PMS_ERR_INVALID, "n out of range [1, 64]");
+    int32_t t_max = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (lengths[i] < l || lengths[i] > PMS_MAX_T)
+            return fail(PMS_ERR_INVALID, "length of sequence " + std::to_string(i) +
+                                             " out of range [l, 2^17]");
+        t_max = std::max(t_max, lengths[i]);
+    }
+    PMS_TRY(validate_shape(n, t_max, l, d));
+    if (cap > 0 && !out_motifs) return fail(PMS_ERR_INVALID, "out_motifs is NULL with capacity > 0");
+    bool empty = false;
+    PMS_TRY(validate_rows_ex(seqs, n, lengths, l, flags, &empty));
+    PMS_TRY(test_hook());
+    if (empty) return PMS_OK;  // a sequence without windows: no l-mer matches all
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    PMS_TRY(init_ctx(g_ctx));
+    g_ctx.t_call = t_call;
+    std::vector<int> status;
+    std::vector<uint64_t> counts;
+    std::vector<double> lat;
+    Shape shape{n, t_max, l, d};
+    shape.lens = lengths;
+    shape.flags = flags;
+    PMS_TRY(solve_instances(g_ctx, {shape}, {seqs}, {out_motifs}, {cap}, status, counts, lat,
+                            false));
     *out_count = counts[0];
     return status[0];
 }

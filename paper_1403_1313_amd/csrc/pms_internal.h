@@ -20,8 +20,8 @@
 typedef struct {
     uint64_t src_off;  // byte offset of the row in the packed input
     uint64_t dst_off;  // uint32 offset of the row's windows
-    int32_t t, l, stride, inst;
-    int32_t layout, reserved;
+    int32_t t, l, stride, inst;  // t: this row's length
+    int32_t layout, flags;        // flags: pms_input_flag bits
 } pms_win_job;
 
 namespace pms {

@@ -98,8 +98,53 @@ __device__ __forceinline__ uint32_t scan_sequence(cu32* W, uint32_t groups, uint
 }  // namespace
 
 // --------------------------------------------------------------------------
-// Steps a1 + a2: encode, pack into LDS, write bit-plane windows.
+// Steps a1 + a2: encode, pack into LDS, write the window table.
+//
+// Window slots of a row: slot w < nw = t-l+1 is the window starting at w;
+// with both strands, slot nw + k is the reverse complement of window k (read
+// backwards, base b -> 3 - b); remaining slots up to the table's stride
+// repeat the row's first window.  With N masking a window holding an N is
+// not a window: its slot repeats the first N-free window instead.  A repeated
+// window cannot change a minimum, so the table holds exactly the row's window
+// set.  (A row with no N-free window is never launched: its instance has no
+// motifs.)
 // --------------------------------------------------------------------------
+namespace {
+
+// Bits [j, j+l) of the N map are all clear (l <= 16; the map has a spare
+// word past the row).
+__device__ __forceinline__ bool n_free(const uint32_t* nbits, int j, int l) {
+    const uint64_t two = (static_cast<uint64_t>(nbits[(j >> 5) + 1]) << 32) | nbits[j >> 5];
+    return ((two >> (j & 31)) & ((1ull << l) - 1)) == 0;
+}
+
+// Source of window slot w: its start and whether it is read as a reverse
+// complement.
+__device__ __forceinline__ void slot_source(int w, int nw, int j0, bool mask_n, bool both,
+                                            const uint32_t* nbits, int l, int& start, bool& rc) {
+    start = j0;
+    rc = false;
+    if (w < nw) {
+        if (!mask_n || n_free(nbits, w, l)) start = w;
+    } else if (both && w < 2 * nw) {
+        const int k = w - nw;
+        if (!mask_n || n_free(nbits, k, l)) {
+            start = k;
+            rc = true;
+        }
+    }
+}
+
+// Base p of the window starting at `start` (reverse complement when rc).
+__device__ __forceinline__ uint32_t slot_base(const uint32_t* packed, int start, bool rc, int p,
+                                              int l) {
+    const int pos = rc ? start + (l - 1 - p) : start + p;
+    const uint32_t b = (packed[pos >> 4] >> (2 * (pos & 15))) & 3u;
+    return rc ? (b ^ 3u) : b;
+}
+
+}  // namespace
+
 extern "C" __global__ void __launch_bounds__(256)
 pms_windows_kernel(const pms_win_job* __restrict__ jobs, const uint8_t* __restrict__ seqs,
                    uint32_t* __restrict__ windows, uint32_t* __restrict__ bad) {
@@ -107,12 +152,25 @@ pms_windows_kernel(const pms_win_job* __restrict__ jobs, const uint8_t* __restri
     const pms_win_job job = jobs[blockIdx.x];
     const uint8_t* row = seqs + job.src_off;
     const int t = job.t, l = job.l, stride = job.stride;
+    const bool mask_n = (job.flags & PMS_INPUT_MASK_N) != 0;
+    const bool both = (job.flags & PMS_INPUT_BOTH_STRANDS) != 0;
     const int words = (t + 15) >> 4;
+    const int nwords = (t + 31) >> 5;
+    uint32_t* const nbits = packed + words + 1;                      // bit q: base q is N
+    int* const first = reinterpret_cast<int*>(nbits + nwords + 1);  // first N-free window
+    const int nw = t - l + 1;
+
+    for (int i = threadIdx.x; i <= nwords; i += blockDim.x) nbits[i] = 0;
+    if (threadIdx.x == 0) {
+        packed[words] = 0;  // a window may read one word past the row
+        *first = nw;
+    }
+    __syncthreads();
 
     // a1: 16 bases per word, base q of the word in bits [2q, 2q+1].
     bool saw_bad = false;
     for (int w = threadIdx.x; w < words; w += blockDim.x) {
-        uint32_t v = 0;
+        uint32_t v = 0, nb = 0;
         const int q_end = min(16, t - 16 * w);
         for (int q = 0; q < q_end; ++q) {
             const uint32_t c = row[16 * w + q] | 0x20u;  // fold upper case onto lower
@@ -121,27 +179,35 @@ pms_windows_kernel(const pms_win_job* __restrict__ jobs, const uint8_t* __restri
             else if (c == 'c') code = 1;
             else if (c == 'g') code = 2;
             else if (c == 't') code = 3;
+            else if (c == 'n' && mask_n) { code = 0; nb |= 1u << q; }
             else { code = 0; saw_bad = true; }
             v |= code << (2 * q);
         }
         packed[w] = v;
+        if (nb) atomicOr(&nbits[w >> 1], nb << (16 * (w & 1)));
     }
-    if (threadIdx.x == 0) packed[words] = 0;  // a window may read one word past the row
     if (saw_bad && bad) bad[job.inst] = 1u;
     __syncthreads();
+    if (mask_n) {
+        for (int j = threadIdx.x; j < nw; j += blockDim.x)
+            if (n_free(nbits, j, l)) {
+                atomicMin(first, j);
+                break;
+            }
+        __syncthreads();
+    }
+    const int j0 = *first < nw ? *first : 0;
 
-    // a2: window j covers bases j .. j+l-1 (l <= 16, so at most two words).
-    const int nw = t - l + 1;
+    // a2: the window slots of the row.
     uint32_t* dst = windows + job.dst_off;
     if (job.layout == PMS_LAYOUT_PLANES) {
         for (int j = threadIdx.x; j < stride; j += blockDim.x) {
-            const int jj = j < nw ? j : 0;
-            const int wq = jj >> 4, sh = 2 * (jj & 15);
-            const uint64_t two = (static_cast<uint64_t>(packed[wq + 1]) << 32) | packed[wq];
-            const uint32_t bits = static_cast<uint32_t>(two >> sh);
+            int start;
+            bool rc;
+            slot_source(j, nw, j0, mask_n, both, nbits, l, start, rc);
             uint32_t hi = 0, lo = 0;
             for (int p = 0; p < l; ++p) {
-                const uint32_t b = (bits >> (2 * p)) & 3u;
+                const uint32_t b = slot_base(packed, start, rc, p, l);
                 hi |= (b >> 1) << (l - 1 - p);
                 lo |= (b & 1u) << (l - 1 - p);
             }
@@ -149,18 +215,18 @@ pms_windows_kernel(const pms_win_job* __restrict__ jobs, const uint8_t* __restri
         }
     } else {
         // Bit-sliced: word (g, p) bit j is the high bit of base p of window
-        // 32g+j, word (g, l+p) the low bit; windows past nw repeat window 0.
-        const int words = stride;  // groups * 2l
-        for (int q = threadIdx.x; q < words; q += blockDim.x) {
+        // slot 32g+j, word (g, l+p) the low bit.
+        const int total = stride;  // groups * 2l
+        for (int q = threadIdx.x; q < total; q += blockDim.x) {
             const int g = q / (2 * l), r = q % (2 * l);
             const int p = r < l ? r : r - l;
             const int plane = r < l ? 1 : 0;
             uint32_t v = 0;
             for (int j = 0; j < 32; ++j) {
-                const int w = 32 * g + j;
-                const int pos = (w < nw ? w : 0) + p;
-                const uint32_t b = (packed[pos >> 4] >> (2 * (pos & 15))) & 3u;
-                v |= ((b >> plane) & 1u) << j;
+                int start;
+                bool rc;
+                slot_source(32 * g + j, nw, j0, mask_n, both, nbits, l, start, rc);
+                v |= ((slot_base(packed, start, rc, p, l) >> plane) & 1u) << j;
             }
             dst[q] = v;
         }
@@ -342,7 +408,9 @@ hipError_t launch_windows(const pms_win_job* jobs, int32_t rows, int32_t max_t,
                           const uint8_t* seqs, uint32_t* windows, uint32_t* bad,
                           hipStream_t stream) {
     if (rows <= 0) return hipSuccess;
-    const size_t lds = (static_cast<size_t>((max_t + 15) / 16) + 1) * sizeof(uint32_t);
+    // packed row + spare word, N map + spare word, first N-free window
+    const size_t lds = (static_cast<size_t>((max_t + 15) / 16) + 1 +
+                        static_cast<size_t>((max_t + 31) / 32) + 1 + 1) * sizeof(uint32_t);
     hipLaunchKernelGGL(pms_windows_kernel, dim3(rows), dim3(256), lds, stream, jobs, seqs,
                        windows, bad);
     return hipGetLastError();

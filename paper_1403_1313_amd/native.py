@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpms.so")
 PMS_OK, PMS_ERR_INVALID, PMS_ERR_OVERFLOW, PMS_ERR_NOMEM, PMS_ERR_DEVICE = range(5)
 PMS_MAX_L, PMS_MAX_N, PMS_MAX_T = 16, 64, 1 << 17
 
-SYMBOLS = ["pms_solve", "pms_solve_many", "pms_decode", "pms_status_string", "pms_last_error",
+SYMBOLS = ["pms_solve", "pms_solve_ex", "pms_solve_many", "pms_decode", "pms_status_string", "pms_last_error",
            "pms_set_config", "pms_get_config", "pms_autotune", "pms_last_stats",
            "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev",
            "pms_valu_probe"]
@@ -45,6 +45,7 @@ class Result(ctypes.Structure):
 
 
 VARIANT_AUTO, VARIANT_LANE, VARIANT_GROUP, VARIANT_GROUP64 = 0, 1, 2, 3
+INPUT_MASK_N, INPUT_BOTH_STRANDS = 1, 2
 VARIANT_NAMES = {1: "lane", 2: "group16", 3: "group64"}
 LAYOUT_PLANES, LAYOUT_BITSLICED = 0, 1
 
@@ -117,6 +118,8 @@ def _load():
     i32 = ctypes.c_int32
     sig = {
         "pms_solve": ([P(ctypes.c_char_p), i32, i32, i32, i32, u32p, u64p], ctypes.c_int),
+        "pms_solve_ex": ([P(ctypes.c_char_p), i32, P(i32), i32, i32, ctypes.c_uint32, u32p, u64p],
+                         ctypes.c_int),
         "pms_solve_many": ([P(Instance), i32, P(Result)], ctypes.c_int),
         "pms_decode": ([ctypes.c_uint32, i32, ctypes.c_char_p], None),
         "pms_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -212,6 +215,37 @@ def solve(seqs, l: int, d: int) -> np.ndarray:
     st, cnt, res = solve_raw(seqs, l, d, capacity=1 << 16)
     if st == PMS_ERR_OVERFLOW:
         st, cnt, res = solve_raw(seqs, l, d, capacity=cnt)
+    _check(st)
+    return res
+
+
+def solve_ex_raw(rows, l: int, d: int, mask_n: bool = False, both: bool = False,
+                 capacity: Optional[int] = None):
+    """pms_solve_ex over rows of their own lengths (list of str/bytes or 1-D
+    uint8 arrays): (status, count, motifs[:min(count, capacity)])."""
+    data = [r.encode() if isinstance(r, str) else
+            (np.ascontiguousarray(r, dtype=np.uint8).tobytes() if isinstance(r, np.ndarray)
+             else bytes(r)) for r in rows]
+    n = len(data)
+    arr = (ctypes.c_char_p * max(n, 1))(*data)
+    lens = (ctypes.c_int32 * max(n, 1))(*[len(r) for r in data])
+    if capacity is None:
+        capacity = 1 << 20
+    out = _out_buffer(capacity)
+    cnt = ctypes.c_uint64(capacity)
+    flags = (INPUT_MASK_N if mask_n else 0) | (INPUT_BOTH_STRANDS if both else 0)
+    st = _lib.pms_solve_ex(arr, n, lens, l, d, flags,
+                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if capacity > 0
+                           else None, ctypes.byref(cnt))
+    k = min(int(cnt.value), capacity)
+    return st, int(cnt.value), out[:k].copy()
+
+
+def solve_ex(rows, l: int, d: int, mask_n: bool = False, both: bool = False) -> np.ndarray:
+    """Sorted uint32 motif codes of pms_solve_ex (regrows on overflow)."""
+    st, cnt, res = solve_ex_raw(rows, l, d, mask_n, both, capacity=1 << 16)
+    if st == PMS_ERR_OVERFLOW:
+        st, cnt, res = solve_ex_raw(rows, l, d, mask_n, both, capacity=cnt)
     _check(st)
     return res
 

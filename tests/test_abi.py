@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 14
+    assert len(names) == 15
     assert sorted(nat.SYMBOLS) == names
     lib = ctypes.CDLL(nat.LIB_PATH)
     for name in names:
@@ -219,3 +219,28 @@ def test_single_hip_runtime_in_process():
     out = subprocess.run([__import__("sys").executable, "-c", code], cwd=ROOT, check=True,
                          capture_output=True, text=True).stdout.strip()
     assert out == "1"
+
+
+def test_solve_ex_rejects_bad_input():
+    """pms_solve_ex argument checks run before any device work."""
+    st, cnt, _ = nat.solve_ex_raw(["ACGTNACG", "ACGT"], 3, 1)
+    assert st == nat.PMS_ERR_INVALID and cnt == 0 and "not A/C/G/T" in nat.last_error()
+    st, _, _ = nat.solve_ex_raw(["ACGTXACG", "ACGT"], 3, 1, mask_n=True)
+    assert st == nat.PMS_ERR_INVALID and "byte 4 of sequence 0" in nat.last_error()
+    st, _, _ = nat.solve_ex_raw(["ACGT", "AC"], 3, 1)
+    assert st == nat.PMS_ERR_INVALID and "length of sequence 1" in nat.last_error()
+    lib = nat.lib()
+    arr = (ctypes.c_char_p * 1)(b"ACGTACGT")
+    lens = (ctypes.c_int32 * 1)(8)
+    cnt = ctypes.c_uint64(0)
+    assert lib.pms_solve_ex(arr, 1, None, 3, 1, 0, None, ctypes.byref(cnt)) == nat.PMS_ERR_INVALID
+    assert lib.pms_solve_ex(arr, 1, lens, 3, 1, 4, None, ctypes.byref(cnt)) == nat.PMS_ERR_INVALID
+    assert lib.pms_solve_ex(arr, 1, lens, 3, 4, 0, None, ctypes.byref(cnt)) == nat.PMS_ERR_INVALID
+
+
+def test_solve_ex_sequence_without_windows_is_empty():
+    """A sequence with no N-free window: no motifs, status OK, no device work
+    (so this holds without a GPU as well)."""
+    st, cnt, res = nat.solve_ex_raw(["ACGTACGT", "ACNNGTNA"], 3, 3, mask_n=True, both=True)
+    assert st == nat.PMS_OK and cnt == 0 and res.size == 0
+
