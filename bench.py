@@ -5,8 +5,9 @@ Default: the (15,4) FM workload (n=20, t=600, seed 0), inputs resident in HBM.
 One step = one whole solve through the device-level C ABI on torch's current
 stream: window building (a1-a2), the persistent search (a3-a6), then the
 motif count and codes copied back and sorted on the host (a7).  Prints one
-JSON line.  ``--mode batched`` / ``--mode serving`` print the batched and
-serving lines instead.
+JSON line.  ``--mode batched`` / ``--mode serving`` / ``--mode ex`` /
+``--mode intersect`` print the batched, serving, real-sequence-options
+(pms_solve_ex) and neighbourhood-intersection lines instead.
 """
 from __future__ import annotations
 
@@ -42,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default="plain",
-                    choices=["plain", "batched", "serving", "probe", "copy"],
+                    choices=["plain", "batched", "serving", "probe", "copy", "ex", "intersect"],
                     help="probe: VALU issue rates; copy: a plain device copy of known size "
                          "(calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--copy-mib", type=int, default=1024)
@@ -261,6 +262,12 @@ def main():
     if args.mode == "batched":
         from paper_1403_1313_amd import benchmarks
         return benchmarks.bench_batched(args)
+    if args.mode == "ex":
+        from paper_1403_1313_amd import benchmarks
+        return benchmarks.bench_ex(args)
+    if args.mode == "intersect":
+        from paper_1403_1313_amd import benchmarks
+        return benchmarks.bench_intersect(args)
     from paper_1403_1313_amd import benchmarks
     return benchmarks.bench_serving(args)
 

@@ -84,6 +84,29 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t 
 int pms_solve_ex(const char* const* seqs, int32_t n, const int32_t* lengths, int32_t l,
                  int32_t d, uint32_t flags, uint32_t* out_motifs, uint64_t* out_count);
 
+/*
+ * pms_solve_intersect -- the same result as pms_solve by a second exact
+ * method: M is the intersection over sequences of the union of the
+ * distance-d neighbourhoods (Hamming balls) of each sequence's windows, the
+ * sample-driven form of the Planted Motif Search family that Section VI names
+ * as future work.  The GPU keeps the candidate space as a 4^l-bit map
+ * (2 x 2^(2l-3) bytes of device memory, 1 GiB at l = 16), sets the bits of
+ * every window's neighbours with atomics, ANDs sequence by sequence, and
+ * stops early when no candidate is left.  Work per sequence: (t-l+1) x
+ * |Ball| bit sets, |Ball| = sum_{k<=d} C(l,k) 3^k; far less than the sweep
+ * when d is small against l, far more when it is not.  Arguments, output and
+ * errors as for pms_solve; PMS_ERR_INVALID also when |Ball| exceeds
+ * PMS_NBHD_MAX_BALL.  Once the candidates left are few enough that checking
+ * them against the remaining sequences costs less than another bitmap pass,
+ * they are checked directly (with the enhanced rule).  pms_last_stats
+ * reports the device time (kernel_ms), the bitmap passes (batches), the bits
+ * set (window_compares) and the direct (candidate, sequence) checks
+ * (seq_visits).
+ */
+#define PMS_NBHD_MAX_BALL (1u << 24)
+int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t d,
+                        uint32_t* out_motifs, uint64_t* out_count);
+
 /* One instance of a batched solve (host buffers). */
 typedef struct {
     const char* const* seqs; /* n pointers to >= t bytes each, as for pms_solve */

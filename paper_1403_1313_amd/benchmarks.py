@@ -191,3 +191,102 @@ def bench_serving(args):
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def bench_ex(args):
+    """pms_solve_ex on the (15,4) workload with real-sequence options: both
+    strands (twice the windows) and 1% N (masked), against the same rows with
+    no options.  (Parity of these inputs is checked in tests/test_gpu_ex.py.)"""
+    import fmgen
+    from . import native as nat
+
+    inst = fmgen.gen_fm(seed=args.seed, **fmgen.PLAIN["plain_15_4"])
+    l, d = inst.l, inst.d
+    rows = [bytes(r) for r in inst.seqs]
+    rng = np.random.default_rng(1403)
+    masked = []
+    for r in rows:
+        b = bytearray(r)
+        for j in np.nonzero(rng.random(len(b)) < 0.01)[0]:
+            b[int(j)] = ord("N")
+        masked.append(bytes(b))
+    cases = {"plain": (rows, False, False), "both_strands": (rows, False, True),
+             "both_strands_masked_1pct": (masked, True, True)}
+    out = {}
+    for name, (rs, mask_n, both) in cases.items():
+        for _ in range(max(1, args.warmup)):
+            nat.solve_ex(rs, l, d, mask_n=mask_n, both=both)
+        walls, kern = [], []
+        for _ in range(args.steps):
+            w0 = time.perf_counter()
+            got = nat.solve_ex(rs, l, d, mask_n=mask_n, both=both)
+            walls.append(time.perf_counter() - w0)
+            kern.append(nat.last_stats()["kernel_ms"])
+        st = nat.last_stats()
+        out[name] = {"wall_ms_median": float(np.median(walls)) * 1e3,
+                     "kernel_ms_median": float(np.median(kern)),
+                     "candidates_per_s": 4 ** l / float(np.median(walls)),
+                     "seq_visits": st["seq_visits"], "window_compares": st["window_compares"],
+                     "motifs": int(got.size)}
+    best = out["both_strands_masked_1pct"]
+    line = {
+        "metric": "candidates/s (both strands, 1% N masked)", "value": best["candidates_per_s"],
+        "unit": "candidates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": best["wall_ms_median"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"FM planted ({l},{d}), n={inst.n}, t={inst.t}, seed {args.seed}, "
+                               "host-level pms_solve_ex; N at 1% of positions (seed 1403)"},
+        "cases": out,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_intersect(args):
+    """Neighbourhood intersection (pms_solve_intersect) against the sweep
+    (pms_solve) on the same FM instances: host-level solves, median wall and
+    device time of each, bits set per second, and where the crossover lies."""
+    import math
+    import fmgen
+    from . import native as nat
+
+    shapes = [(11, 3, 20, 600), (13, 4, 20, 600), (15, 4, 20, 600), (16, 3, 20, 600),
+              (16, 2, 20, 600), (14, 1, 20, 600)]
+    rows = []
+    for (l, d, n, t) in shapes:
+        inst = fmgen.gen_fm(l, d, n, t, args.seed)
+        res = {}
+        for name, fn in (("sweep", nat.solve), ("intersect", nat.solve_intersect)):
+            for _ in range(max(1, args.warmup)):
+                got = fn(inst.seqs, l, d)
+            walls, dev = [], []
+            for _ in range(max(1, args.steps // 4)):
+                w0 = time.perf_counter()
+                got = fn(inst.seqs, l, d)
+                walls.append(time.perf_counter() - w0)
+                dev.append(nat.last_stats()["kernel_ms"])
+            st = nat.last_stats()
+            res[name] = {"wall_ms": float(np.median(walls)) * 1e3,
+                         "device_ms": float(np.median(dev)),
+                         "motifs": int(got.size), "codes_sha": _sha(got)}
+            if name == "intersect":
+                res[name]["bits_set_per_s"] = st["window_compares"] / (np.median(dev) * 1e-3)
+                res[name]["sequences_processed"] = st["batches"]
+        ball = sum(math.comb(l, k) * 3 ** k for k in range(d + 1))
+        rows.append({"l": l, "d": d, "n": n, "t": t, "ball": ball,
+                     "same_result": res["sweep"]["codes_sha"] == res["intersect"]["codes_sha"],
+                     "faster": min(res, key=lambda k: res[k]["wall_ms"]), **res})
+    line = {
+        "metric": "intersect vs sweep wall-time ratio at (16,2)",
+        "value": next(r for r in rows if (r["l"], r["d"]) == (16, 2))["sweep"]["wall_ms"]
+        / next(r for r in rows if (r["l"], r["d"]) == (16, 2))["intersect"]["wall_ms"],
+        "unit": "x", "n_gpus": 1, "steps": max(1, args.steps // 4), "warmup": args.warmup,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "FM planted instances, n=20, t=600, seed "
+                               f"{args.seed}, both exact methods through the host-level C ABI"},
+        "shapes": rows,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+

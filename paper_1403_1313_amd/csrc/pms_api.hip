@@ -19,6 +19,7 @@
 #include <mutex>
 #include <numeric>
 #include <chrono>
+#include <functional>
 #include <map>
 #include <sstream>
 #include <string>
@@ -325,6 +326,9 @@ struct Ctx {
     std::chrono::steady_clock::time_point t_call;
     // launch shapes by (variant, max_n, wg_waves, wgs_per_cu)
     std::map<uint64_t, Shape2> shapes;
+    // neighbourhood-intersection method: bitmaps, window codes, ball masks
+    DevBuf nb_m, nb_b, nb_codes, nb_deltas, nb_cand, nb_out, nb_count;
+    int32_t nb_ball_l = -1, nb_ball_d = -1, nb_ball_size = 0;
 };
 
 Ctx g_ctx;
@@ -966,6 +970,158 @@ int pms_solve_ex(const char* const* seqs, int32_t n, const int32_t* lengths, int
                             false));
     *out_count = counts[0];
     return status[0];
+}
+
+// XOR masks of the distance-d ball around an l-mer code: every choice of at
+// most d of the l 2-bit digits, each changed to one of the other three bases
+// (digit XOR 1, 2 or 3).  |Ball| = sum_{k<=d} C(l,k) 3^k.
+void ball_masks(int32_t l, int32_t d, std::vector<uint32_t>& out) {
+    out.clear();
+    std::vector<int32_t> pos;
+    std::function<void(int32_t, uint32_t)> rec = [&](int32_t start, uint32_t mask) {
+        out.push_back(mask);
+        if (static_cast<int32_t>(pos.size()) == d) return;
+        for (int32_t p = start; p < l; ++p) {
+            pos.push_back(p);
+            for (uint32_t g = 1; g <= 3; ++g) rec(p + 1, mask | (g << (2 * (l - 1 - p))));
+            pos.pop_back();
+        }
+    };
+    rec(0, 0u);
+}
+
+uint64_t ball_size(int32_t l, int32_t d) {
+    uint64_t total = 0, binom = 1, pow3 = 1;
+    for (int32_t k = 0; k <= d; ++k) {
+        if (k > 0) {
+            binom = binom * static_cast<uint64_t>(l - k + 1) / static_cast<uint64_t>(k);
+            pow3 *= 3;
+        }
+        total += binom * pow3;
+    }
+    return total;
+}
+
+int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t d,
+                        uint32_t* out_motifs, uint64_t* out_count) {
+    const auto t_call = std::chrono::steady_clock::now();
+    g_last_error.clear();
+    if (!out_count) return fail(PMS_ERR_INVALID, "out_count is NULL");
+    const uint64_t cap = *out_count;
+    *out_count = 0;
+    PMS_TRY(validate_shape(n, t, l, d));
+    if (cap > 0 && !out_motifs) return fail(PMS_ERR_INVALID, "out_motifs is NULL with capacity > 0");
+    if (ball_size(l, d) > PMS_NBHD_MAX_BALL)
+        return fail(PMS_ERR_INVALID, "distance-d ball larger than PMS_NBHD_MAX_BALL masks");
+    PMS_TRY(validate_rows(seqs, n, t));
+    PMS_TRY(test_hook());
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    PMS_TRY(init_ctx(c));
+    hipStream_t s = c.stream;
+    const int32_t nw = t - l + 1;
+    const uint64_t bits = 1ull << (2 * l);
+    const uint64_t words = align_up(std::max<uint64_t>(1, bits / 32), 4);  // whole 16-byte vectors
+    if (c.nb_ball_l != l || c.nb_ball_d != d) {
+        std::vector<uint32_t> masks;
+        ball_masks(l, d, masks);
+        PMS_TRY(c.nb_deltas.ensure(masks.size() * 4));
+        PMS_HIP(hipMemcpy(c.nb_deltas.p, masks.data(), masks.size() * 4, hipMemcpyHostToDevice));
+        c.nb_ball_l = l;
+        c.nb_ball_d = d;
+        c.nb_ball_size = static_cast<int32_t>(masks.size());
+    }
+    const int32_t nd = c.nb_ball_size;
+    PMS_TRY(c.d_raw.ensure(std::max<size_t>(static_cast<size_t>(n) * t, 256)));
+    PMS_TRY(c.h_raw.ensure(std::max<size_t>(static_cast<size_t>(n) * t, 256)));
+    PMS_TRY(c.nb_codes.ensure(static_cast<size_t>(n) * nw * 4));
+    PMS_TRY(c.nb_m.ensure(words * 4));
+    PMS_TRY(c.nb_b.ensure(words * 4));
+    PMS_TRY(c.nb_count.ensure(256));
+    PMS_TRY(c.h_back.ensure(256));
+    for (int32_t r = 0; r < n; ++r) memcpy(c.h_raw.as<char>(static_cast<size_t>(r) * t), seqs[r], t);
+    const double prep_ms = ms_since(t_call);
+    uint32_t* m = c.nb_m.as<uint32_t>();
+    uint32_t* b = c.nb_b.as<uint32_t>();
+    auto* cnt = c.nb_count.as<unsigned long long>();
+    auto* h_cnt = c.h_back.as<unsigned long long>();
+    const uint32_t grid = static_cast<uint32_t>(c.cus) * 16u;
+    PMS_HIP(hipEventRecord(c.ev[0], s));
+    PMS_HIP(hipMemcpyAsync(c.d_raw.p, c.h_raw.p, static_cast<size_t>(n) * t, hipMemcpyHostToDevice, s));
+    PMS_HIP(pms::launch_nbhd_codes(c.d_raw.as<uint8_t>(), t, l, n, c.nb_codes.as<uint32_t>(), s));
+    // Bitmap passes while they are the cheaper way on: once the candidates
+    // left are few, checking them against the remaining sequences directly
+    // costs less than another pass (scatter plus three sweeps of the maps).
+    // Rates are round figures for one MI355X.
+    constexpr double kBitsPerS = 3e10, kStreamBytesPerS = 4e12, kComparesPerS = 5e12;
+    const double pass_s = static_cast<double>(nw) * nd / kBitsPerS +
+                          3.0 * static_cast<double>(words) * 4.0 / kStreamBytesPerS;
+    uint64_t left = 0, visits = 0;
+    int32_t scanned = 0;
+    bool verified = false;
+    for (int32_t i = 0; i < n; ++i) {
+        uint32_t* target = i == 0 ? m : b;
+        PMS_HIP(pms::launch_nbhd_zero(target, words, grid, s));
+        PMS_HIP(pms::launch_fill(reinterpret_cast<uint32_t*>(cnt), 8, 0u, s));
+        // The first sequence's map is M; its scatter counts the bits it sets.
+        PMS_HIP(pms::launch_nbhd_scatter(c.nb_codes.as<uint32_t>() + static_cast<size_t>(i) * nw, nw,
+                                         c.nb_deltas.as<uint32_t>(), nd, target,
+                                         i == 0 ? cnt : nullptr, grid, s));
+        if (i > 0) PMS_HIP(pms::launch_nbhd_and(m, b, words, cnt, grid, s));  // M &= B
+        PMS_HIP(hipMemcpyAsync(h_cnt, cnt, 8, hipMemcpyDeviceToHost, s));
+        PMS_HIP(hipStreamSynchronize(s));
+        left = h_cnt[0];
+        ++scanned;
+        if (left == 0 || i + 1 == n) break;
+        const double verify_s = static_cast<double>(left) * nw * 1.1 / kComparesPerS;
+        if (verify_s > pass_s) continue;
+        // The candidates left, then sequences i+1 .. n-1 checked directly.
+        PMS_TRY(c.nb_cand.ensure(left * 4));
+        PMS_TRY(c.nb_out.ensure(left * 4));
+        PMS_HIP(pms::launch_fill(reinterpret_cast<uint32_t*>(cnt), 2, 0u, s));  // collect count
+        PMS_HIP(pms::launch_nbhd_collect(m, words, c.nb_cand.as<uint32_t>(), left, cnt, grid, s));
+        PMS_HIP(pms::launch_nbhd_verify(c.nb_cand.as<uint32_t>(), left, c.nb_codes.as<uint32_t>(), nw,
+                                        i + 1, n, d, c.nb_out.as<uint32_t>(), left, cnt + 1, cnt + 2,
+                                        grid, s));
+        PMS_HIP(hipEventRecord(c.ev[2], s));
+        PMS_HIP(hipMemcpyAsync(h_cnt, cnt, 24, hipMemcpyDeviceToHost, s));
+        PMS_HIP(hipStreamSynchronize(s));
+        if (h_cnt[0] != left) return fail(PMS_ERR_DEVICE, "collected count differs from the AND count");
+        left = h_cnt[1];
+        visits = h_cnt[2];
+        verified = true;
+        break;
+    }
+    if (!verified) {
+        PMS_TRY(c.nb_out.ensure(std::max<uint64_t>(left, 1) * 4));
+        PMS_HIP(pms::launch_fill(reinterpret_cast<uint32_t*>(cnt), 2, 0u, s));
+        if (left)
+            PMS_HIP(pms::launch_nbhd_collect(m, words, c.nb_out.as<uint32_t>(), left, cnt, grid, s));
+        PMS_HIP(hipEventRecord(c.ev[2], s));
+        PMS_HIP(hipMemcpyAsync(h_cnt, cnt, 8, hipMemcpyDeviceToHost, s));
+        PMS_HIP(hipStreamSynchronize(s));
+        if (left && h_cnt[0] != left)
+            return fail(PMS_ERR_DEVICE, "collected count differs from the AND count");
+    }
+    const auto t_back = std::chrono::steady_clock::now();
+    std::vector<uint32_t> codes(left);
+    if (left)
+        PMS_HIP(hipMemcpy(codes.data(), c.nb_out.p, left * 4, hipMemcpyDeviceToHost));
+    std::sort(codes.begin(), codes.end());
+    const uint64_t k = std::min<uint64_t>(cap, left);
+    if (k) memcpy(out_motifs, codes.data(), k * 4);
+    float ms = 0;
+    PMS_HIP(hipEventElapsedTime(&ms, c.ev[0], c.ev[2]));
+    c.last = pms_stats{};
+    c.last.kernel_ms = ms;
+    c.last.batches = static_cast<uint64_t>(scanned);
+    c.last.window_compares = static_cast<uint64_t>(scanned) * nw * static_cast<uint64_t>(nd);
+    c.last.seq_visits = visits;
+    c.last.host_prep_ms = prep_ms;
+    c.last.host_finish_ms = ms_since(t_back);
+    c.last_pending = false;
+    *out_count = left;
+    return left > cap ? fail(PMS_ERR_OVERFLOW, "more motifs than capacity") : PMS_OK;
 }
 
 int pms_solve_many(const pms_instance* inst, int32_t count, pms_result* results) {

@@ -36,6 +36,23 @@ hipError_t launch_search(const pms_dev_instance* insts, const pms_work_item* wor
 
 hipError_t launch_fill(uint32_t* p, uint64_t words, uint32_t v, hipStream_t stream);
 
+// Neighbourhood-intersection method (pms_nbhd.hip).
+hipError_t launch_nbhd_codes(const uint8_t* seqs, int32_t t, int32_t l, int32_t rows,
+                             uint32_t* codes, hipStream_t stream);
+// Bitmap lengths in words are multiples of 4 (16-byte vectors).
+hipError_t launch_nbhd_zero(uint32_t* p, uint64_t words, uint32_t grid, hipStream_t stream);
+hipError_t launch_nbhd_scatter(const uint32_t* codes, int32_t nw, const uint32_t* deltas,
+                               int32_t nd, uint32_t* bitmap, unsigned long long* fresh,
+                               uint32_t grid, hipStream_t stream);
+hipError_t launch_nbhd_and(uint32_t* m, const uint32_t* b, uint64_t words,
+                           unsigned long long* count, uint32_t grid, hipStream_t stream);
+hipError_t launch_nbhd_collect(const uint32_t* m, uint64_t words, uint32_t* out, uint64_t cap,
+                               unsigned long long* count, uint32_t grid, hipStream_t stream);
+hipError_t launch_nbhd_verify(const uint32_t* cand, uint64_t count, const uint32_t* codes,
+                              int32_t nw, int32_t s_begin, int32_t n, int32_t d, uint32_t* out,
+                              uint64_t cap, unsigned long long* out_count,
+                              unsigned long long* visits, uint32_t grid, hipStream_t stream);
+
 const void* search_kernel_symbol();
 
 // Where a grouped launch keeps its stage queues: the first lds_stages in LDS,

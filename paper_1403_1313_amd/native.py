@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpms.so")
 PMS_OK, PMS_ERR_INVALID, PMS_ERR_OVERFLOW, PMS_ERR_NOMEM, PMS_ERR_DEVICE = range(5)
 PMS_MAX_L, PMS_MAX_N, PMS_MAX_T = 16, 64, 1 << 17
 
-SYMBOLS = ["pms_solve", "pms_solve_ex", "pms_solve_many", "pms_decode", "pms_status_string", "pms_last_error",
+SYMBOLS = ["pms_solve", "pms_solve_ex", "pms_solve_intersect", "pms_solve_many", "pms_decode", "pms_status_string", "pms_last_error",
            "pms_set_config", "pms_get_config", "pms_autotune", "pms_last_stats",
            "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev",
            "pms_valu_probe"]
@@ -120,6 +120,7 @@ def _load():
         "pms_solve": ([P(ctypes.c_char_p), i32, i32, i32, i32, u32p, u64p], ctypes.c_int),
         "pms_solve_ex": ([P(ctypes.c_char_p), i32, P(i32), i32, i32, ctypes.c_uint32, u32p, u64p],
                          ctypes.c_int),
+        "pms_solve_intersect": ([P(ctypes.c_char_p), i32, i32, i32, i32, u32p, u64p], ctypes.c_int),
         "pms_solve_many": ([P(Instance), i32, P(Result)], ctypes.c_int),
         "pms_decode": ([ctypes.c_uint32, i32, ctypes.c_char_p], None),
         "pms_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -246,6 +247,30 @@ def solve_ex(rows, l: int, d: int, mask_n: bool = False, both: bool = False) -> 
     st, cnt, res = solve_ex_raw(rows, l, d, mask_n, both, capacity=1 << 16)
     if st == PMS_ERR_OVERFLOW:
         st, cnt, res = solve_ex_raw(rows, l, d, mask_n, both, capacity=cnt)
+    _check(st)
+    return res
+
+
+def solve_intersect_raw(seqs, l: int, d: int, capacity: Optional[int] = None):
+    """pms_solve_intersect: (status, count, motifs[:min(count, capacity)])."""
+    arr, keep, n, t = _rows(seqs)
+    if capacity is None:
+        capacity = 1 << 20
+    out = _out_buffer(capacity)
+    cnt = ctypes.c_uint64(capacity)
+    st = _lib.pms_solve_intersect(arr, n, t, l, d,
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+                                  if capacity > 0 else None, ctypes.byref(cnt))
+    del keep
+    k = min(int(cnt.value), capacity)
+    return st, int(cnt.value), out[:k].copy()
+
+
+def solve_intersect(seqs, l: int, d: int) -> np.ndarray:
+    """Sorted uint32 motif codes by the neighbourhood-intersection method."""
+    st, cnt, res = solve_intersect_raw(seqs, l, d, capacity=1 << 16)
+    if st == PMS_ERR_OVERFLOW:
+        st, cnt, res = solve_intersect_raw(seqs, l, d, capacity=cnt)
     _check(st)
     return res
 

@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 15
+    assert len(names) == 16
     assert sorted(nat.SYMBOLS) == names
     lib = ctypes.CDLL(nat.LIB_PATH)
     for name in names:
@@ -243,4 +243,12 @@ def test_solve_ex_sequence_without_windows_is_empty():
     (so this holds without a GPU as well)."""
     st, cnt, res = nat.solve_ex_raw(["ACGTACGT", "ACNNGTNA"], 3, 3, mask_n=True, both=True)
     assert st == nat.PMS_OK and cnt == 0 and res.size == 0
+
+
+def test_solve_intersect_rejects_large_balls():
+    """The ball-size limit is checked before any device work."""
+    st, cnt, _ = nat.solve_intersect_raw(["ACGT" * 8], 16, 10)
+    assert st == nat.PMS_ERR_INVALID and cnt == 0 and "PMS_NBHD_MAX_BALL" in nat.last_error()
+    st, _, _ = nat.solve_intersect_raw(["ACGTNACGTACG"], 4, 1)
+    assert st == nat.PMS_ERR_INVALID and "not A/C/G/T" in nat.last_error()
 
