@@ -59,10 +59,29 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(seqs, l, d, target_s):
-    """The oracle (brute mode, unmodified) on a bounded prefix of the candidate space."""
+def oracle_rate(seqs, l, d, mode, threads, seconds):
+    """Candidates/s of the oracle over a prefix of the candidate space sized to
+    take about `seconds`; (rate, span, elapsed)."""
     import oracle
-    threads = os.cpu_count() or 1
+    span = 1 << 10
+    while True:
+        t0 = time.perf_counter()
+        oracle.solve(seqs, l, d, mode=mode, threads=threads, k_range=(0, span))
+        dt = time.perf_counter() - t0
+        if dt >= seconds / 4 or span >= 4 ** l:
+            break
+        span = min(4 ** l, int(span * max(2.0, min(16.0, seconds / 4 / max(dt, 1e-3)))))
+    return span / dt, span, dt
+
+
+def cpu_baseline(seqs, l, d, target_s):
+    """The oracle (brute mode, unmodified) on a bounded prefix of the candidate
+    space; beside it the oracle's skip mode (the paper's own CPU method,
+    Section III.A) on the same instance, and skip mode on one thread for the
+    (11,3) shape, the framing of the paper's speedups over one thread."""
+    import oracle
+    import fmgen
+    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
     span = 1 << 14
     while True:
         t0 = time.perf_counter()
@@ -76,9 +95,17 @@ def cpu_baseline(seqs, l, d, target_s):
         t0 = time.perf_counter()
         oracle.solve(seqs, l, d, mode="brute", threads=threads, k_range=(0, span))
         dt = time.perf_counter() - t0
+    skip_rate, skip_span, skip_dt = oracle_rate(seqs, l, d, "skip", threads, 3.0)
+    inst11 = fmgen.gen_fm(seed=0, **fmgen.PLAIN["plain_11_3"])
+    one_rate, one_span, one_dt = oracle_rate(inst11.seqs, 11, 3, "skip", 1, 3.0)
     return {"value": span / dt, "unit": "candidates/s", "cores": threads, "kind": "oracle",
             "sample": f"brute-mode oracle over candidates [0, {span}) of the same instance "
-                      f"({span / 4 ** l:.2e} of 4^{l}), {dt:.1f} s on {threads} host threads"}
+                      f"({span / 4 ** l:.2e} of 4^{l}), {dt:.1f} s on {threads} host threads",
+            "skip_mode": {"value": skip_rate, "unit": "candidates/s", "cores": threads,
+                          "sample": f"candidates [0, {skip_span}), {skip_dt:.1f} s"},
+            "one_thread_skip_11_3": {"value": one_rate, "unit": "candidates/s", "cores": 1,
+                                     "sample": f"(11,3) n=20 t=600 seed 0, candidates "
+                                               f"[0, {one_span}), {one_dt:.1f} s"}}
 
 
 def code_text(src):
