@@ -246,6 +246,10 @@ Estimate estimate(const Shape& s) {
     return {cands * pk + 1.0, ev};
 }
 
+// Batch::out_cap value asking for no device output at all (a size query:
+// the kernel's count is exact without it).
+constexpr uint64_t kCountOnly = ~0ull;
+
 // Device output slots reserved for one instance before its count is known.
 // PMS_TEST_DEVICE_CAP=<k> caps the reservation (tests of the rerun path).
 uint64_t output_capacity(const Shape& s) {
@@ -494,7 +498,8 @@ void plan_batch(Batch& b, const pms_config& cfg, uint64_t target_items) {
         b.raw_off[i] = b.raw_bytes;
         b.win_off[i] = b.win_words;
         b.out_off[i] = b.out_words;
-        if (b.out_cap[i] == 0) b.out_cap[i] = output_capacity(s);
+        if (b.out_cap[i] == kCountOnly) b.out_cap[i] = 0;  // size query: no device codes
+        else if (b.out_cap[i] == 0) b.out_cap[i] = output_capacity(s);
         size_t row_off = 0;  // rows are packed back to back
         for (int32_t r = 0; r < s.n; ++r) {
             b.jobs.push_back({b.raw_off[i] + row_off, b.win_off[i] + static_cast<size_t>(r) * stride,
@@ -679,7 +684,8 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     Batch b;
     b.shape = shapes;
     b.rows = rows;
-    b.out_cap.assign(m, 0);
+    b.out_cap.resize(m);
+    for (size_t i = 0; i < m; ++i) b.out_cap[i] = caps[i] == 0 ? kCountOnly : 0;
     plan_batch(b, cfg, target_items(c));
     PMS_TRY(stage_batch(c, b));
     const double prep_ms = ms_since(c.t_call);
@@ -701,7 +707,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
         if (bad[i]) status[i] = fail(PMS_ERR_INVALID, "a byte is not A/C/G/T");
         if (st[i].items_left != 0 || ctr->error)
             return fail(PMS_ERR_DEVICE, "search ended with unfinished work items");
-        if (counts[i] > b.out_cap[i]) rerun.push_back(i);
+        if (caps[i] > 0 && counts[i] > b.out_cap[i]) rerun.push_back(i);
     }
     c.last.seq_visits = visits;
     c.last.window_compares = wcmp;
@@ -713,11 +719,13 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     // the device estimate are solved again with the exact capacity (the count
     // is exact, so one rerun suffices) once those copies have landed.
     std::vector<size_t> seg(m + 1, 0);
-    for (size_t i = 0; i < m; ++i) seg[i + 1] = seg[i] + (status[i] == PMS_OK ? counts[i] : 0);
+    // (A size query, capacity 0, needs the count only: no codes come back.)
+    for (size_t i = 0; i < m; ++i)
+        seg[i + 1] = seg[i] + (status[i] == PMS_OK && caps[i] > 0 ? counts[i] : 0);
     PMS_TRY(c.h_out.ensure(std::max<size_t>(seg[m] * 4, 256)));
     uint32_t* const h_codes = c.h_out.as<uint32_t>();
     for (size_t i = 0; i < m; ++i)
-        if (status[i] == PMS_OK && counts[i] && counts[i] <= b.out_cap[i])
+        if (status[i] == PMS_OK && caps[i] > 0 && counts[i] && counts[i] <= b.out_cap[i])
             PMS_HIP(hipMemcpyAsync(h_codes + seg[i], c.d_out.as<uint32_t>() + b.out_off[i],
                                    counts[i] * 4, hipMemcpyDeviceToHost, c.stream));
     PMS_HIP(hipStreamSynchronize(c.stream));
