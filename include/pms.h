@@ -283,7 +283,9 @@ int32_t pms_window_stride(int32_t t, int32_t l, int32_t layout);
  * layout)].  PLANES: window j is (high-bit plane of base p in bit 16+l-1-p,
  * low-bit plane in bit l-1-p).  BITSLICED: see pms_layout.  Window slots past
  * t-l+1 repeat window 0.  Bytes that are not A/C/G/T (either case) set
- * *dev_bad (device uint32) to 1; dev_bad may be NULL.
+ * *dev_bad (device uint32) to 1; dev_bad may be NULL.  Asynchronous on
+ * `stream`; the call does not wait for work already queued there (its job
+ * table goes through one of 8 staging slots that are reused in turn).
  */
 int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t layout,
                       uint32_t* dev_windows, uint32_t* dev_bad, void* stream);

@@ -330,6 +330,16 @@ struct Ctx {
     std::chrono::steady_clock::time_point t_call;
     // launch shapes by (variant, max_n, wg_waves, wgs_per_cu)
     std::map<uint64_t, Shape2> shapes;
+    // pms_build_windows job tables: a ring of pinned and device slots, each
+    // reused only once its copy (from kJobRing calls before) has run, so a
+    // call never waits for work queued ahead of it on the stream.
+    static constexpr int kJobRing = 8;
+    static constexpr size_t kJobSlot = 4096;  // >= PMS_MAX_N jobs
+    HostBuf bw_host;
+    DevBuf bw_dev;
+    hipEvent_t bw_ev[kJobRing] = {};
+    bool bw_live[kJobRing] = {};
+    int bw_next = 0;
     // neighbourhood-intersection method: bitmaps, window codes, ball masks
     DevBuf nb_m, nb_b, nb_codes, nb_deltas, nb_cand, nb_out, nb_count;
     int32_t nb_ball_l = -1, nb_ball_d = -1, nb_ball_size = 0;
@@ -1232,22 +1242,26 @@ int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, 
     Ctx& c = g_ctx;
     PMS_TRY(init_ctx(c));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // Job table through the device workspace; wait for the previous upload
-    // from the pinned mirror before overwriting it.
-    if (c.dv_copy_live) PMS_HIP(hipEventSynchronize(c.dv_copied));
-    const size_t bytes = align_up(static_cast<size_t>(n) * sizeof(pms_win_job), 256);
-    PMS_TRY(c.hv_meta.ensure(bytes));
-    PMS_TRY(c.dv_meta.ensure(bytes));
-    c.dv_plan_valid = false;  // dv_meta is about to hold other data
-    pms_win_job* jobs = c.hv_meta.as<pms_win_job>();
+    static_assert(PMS_MAX_N * sizeof(pms_win_job) <= Ctx::kJobSlot, "job slot too small");
+    PMS_TRY(c.bw_host.ensure(Ctx::kJobRing * Ctx::kJobSlot));
+    PMS_TRY(c.bw_dev.ensure(Ctx::kJobRing * Ctx::kJobSlot));
+    const int slot = c.bw_next;
+    c.bw_next = (slot + 1) % Ctx::kJobRing;
+    if (!c.bw_ev[slot]) PMS_HIP(hipEventCreateWithFlags(&c.bw_ev[slot], hipEventDisableTiming));
+    if (c.bw_live[slot]) PMS_HIP(hipEventSynchronize(c.bw_ev[slot]));
+    char* h = c.bw_host.as<char>(slot * Ctx::kJobSlot);
+    char* dv = c.bw_dev.as<char>(slot * Ctx::kJobSlot);
+    pms_win_job* jobs = reinterpret_cast<pms_win_job*>(h);
     const int32_t stride = window_stride(t, l, layout);
     for (int32_t r = 0; r < n; ++r)
         jobs[r] = {static_cast<uint64_t>(r) * t, static_cast<uint64_t>(r) * stride, t, l, stride, 0,
                    layout, 0};
-    PMS_HIP(hipMemcpyAsync(c.dv_meta.p, c.hv_meta.p, bytes, hipMemcpyHostToDevice, s));
-    PMS_HIP(hipEventRecord(c.dv_copied, s));
-    c.dv_copy_live = true;
-    PMS_HIP(pms::launch_windows(c.dv_meta.as<pms_win_job>(), n, t, dev_seqs, dev_windows, dev_bad, s));
+    PMS_HIP(hipMemcpyAsync(dv, h, static_cast<size_t>(n) * sizeof(pms_win_job),
+                           hipMemcpyHostToDevice, s));
+    PMS_HIP(hipEventRecord(c.bw_ev[slot], s));
+    c.bw_live[slot] = true;
+    PMS_HIP(pms::launch_windows(reinterpret_cast<const pms_win_job*>(dv), n, t, dev_seqs,
+                                dev_windows, dev_bad, s));
     return PMS_OK;
 }
 
