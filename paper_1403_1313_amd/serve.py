@@ -116,7 +116,7 @@ class Server:
     def __init__(self, mem_budget: int = 256 << 20, step_ms: float = 2.0,
                  max_inflight: int = 2, compares_per_s: float = 2.5e14,
                  device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
-                 items_per_step: int = 8192):
+                 items_per_step: int = 8192, oldest_share: float = 0.5):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)
@@ -129,6 +129,7 @@ class Server:
         self.rate = float(compares_per_s)
         self.step_compares = self.step_s * self.rate
         self.items_per_step = int(items_per_step)
+        self.oldest_share = float(oldest_share)
         self.copy_stream = torch.cuda.Stream(self.dev)
         self.max_inflight = int(max_inflight)
         # Steps run a grouped kernel, whose windows are bit-sliced: 64
@@ -267,8 +268,8 @@ class Server:
         buf.budget = budget
         oldest = min(live, key=lambda r: r.arrival)
         order = sorted(live, key=lambda r: (r.total - r.cursor) * r.cost_per_cand)
-        shares = {oldest.rid: 0.5 * budget}
-        left = 0.5 * budget
+        shares = {oldest.rid: self.oldest_share * budget}
+        left = (1.0 - self.oldest_share) * budget
         for r in order:
             want = (r.total - r.cursor) * r.cost_per_cand - shares.get(r.rid, 0.0)
             give = min(max(want, 0.0), left)
@@ -290,6 +291,9 @@ class Server:
             if room <= 0:
                 break
             size = int(item_compares / r.cost_per_cand)
+            # A small request is still spread over up to ~1024 items (whole
+            # 64-candidate groups), so that it runs on many wavefronts.
+            size = min(size, max(64, cands // 1024))
             size = max(64, (size + 63) // 64 * 64)
             k = min(-(-cands // size), room)
             begins = r.cursor + np.arange(k, dtype=np.uint64) * np.uint64(size)
