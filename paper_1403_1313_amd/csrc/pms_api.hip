@@ -677,6 +677,38 @@ int run_batch(Ctx& c, Batch& b, const pms_config& cfg, bool use_graph) {
     return PMS_OK;
 }
 
+// Ascending order of k motif codes of `bits` significant bits (2l).  Small
+// sets go to std::sort; larger ones to a least-significant-digit radix sort
+// with at most 11-bit digits (two passes up to l = 11, three up to l = 16),
+// which is several times faster than a comparison sort at 10^5 codes.
+void sort_codes(uint32_t* v, size_t k, int bits, std::vector<uint32_t>& tmp) {
+    if (k < 4096 || bits <= 0) {
+        std::sort(v, v + k);
+        return;
+    }
+    const int passes = (bits + 10) / 11;
+    const int w = (bits + passes - 1) / passes;
+    const uint32_t buckets = 1u << w, digit = buckets - 1;
+    tmp.resize(k);
+    std::vector<size_t> hist(buckets);
+    uint32_t* src = v;
+    uint32_t* dst = tmp.data();
+    for (int pass = 0; pass < passes; ++pass) {
+        const int sh = pass * w;
+        std::fill(hist.begin(), hist.end(), 0);
+        for (size_t i = 0; i < k; ++i) ++hist[(src[i] >> sh) & digit];
+        size_t sum = 0;
+        for (uint32_t b = 0; b < buckets; ++b) {
+            const size_t h = hist[b];
+            hist[b] = sum;
+            sum += h;
+        }
+        for (size_t i = 0; i < k; ++i) dst[hist[(src[i] >> sh) & digit]++] = src[i];
+        std::swap(src, dst);
+    }
+    if (src != v) memcpy(v, src, k * 4);
+}
+
 bool use_graph_default() {
     const char* v = getenv("PMS_NO_GRAPH");
     return !(v && *v && *v != '0');
@@ -759,11 +791,12 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     std::atomic<size_t> next{0};
     std::atomic<bool> dup{false};
     auto worker = [&]() {
+        std::vector<uint32_t> tmp;
         for (size_t i = next++; i < m; i = next++) {
             if (status[i] != PMS_OK) continue;
             uint32_t* const v = h_codes + seg[i];
             const size_t k_all = seg[i + 1] - seg[i];
-            std::sort(v, v + k_all);
+            sort_codes(v, k_all, 2 * shapes[i].l, tmp);
             if (std::adjacent_find(v, v + k_all) != v + k_all) {
                 dup = true;
                 continue;
@@ -1125,7 +1158,8 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
     std::vector<uint32_t> codes(left);
     if (left)
         PMS_HIP(hipMemcpy(codes.data(), c.nb_out.p, left * 4, hipMemcpyDeviceToHost));
-    std::sort(codes.begin(), codes.end());
+    std::vector<uint32_t> tmp;
+    sort_codes(codes.data(), codes.size(), 2 * l, tmp);
     const uint64_t k = std::min<uint64_t>(cap, left);
     if (k) memcpy(out_motifs, codes.data(), k * 4);
     float ms = 0;
