@@ -214,8 +214,9 @@ typedef struct {
                                 algorithmic window-compare count */
     uint64_t batches;        /* wavefront sequence scans executed */
     uint64_t window_compares;/* sum over instances of seq_visits x (t-l+1) */
-    uint64_t candidate_slots;/* candidate scan slots executed: batches x 64 x (1, 16 or 64
-                                candidates per lane) */
+    uint64_t candidate_slots;/* candidate scan slots executed: 64 per lane-candidate of
+                                each batch (1, 16 or 64 per lane; 1 in GROUP64's
+                                single-candidate scans) */
     uint32_t grid;           /* workgroups launched */
     uint32_t wg_waves;
     uint32_t chunk;
@@ -326,6 +327,7 @@ typedef struct {
     uint32_t error;      /* set to 1 if an instance had n > max_n (its items are skipped) */
     uint64_t batches;    /* 64-lane sequence scans executed */
     uint64_t t_start;    /* realtime stamp of the first claim */
+    uint64_t single_batches; /* of those, scans of one candidate per lane (GROUP64) */
 } pms_dev_counters;
 
 /*

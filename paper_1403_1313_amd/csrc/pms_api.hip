@@ -416,16 +416,16 @@ int query_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, 
     if (variant == PMS_VARIANT_LANE) {
         per_wave = static_cast<size_t>(pms::queue_words(max_n, variant) + PMS_OUTBUF) * 4;
     } else {
-        const uint32_t entry = variant == PMS_VARIANT_GROUP64 ? 3u : 2u;
+        const uint32_t entry = pms::stage_queue_words(variant == PMS_VARIANT_GROUP64 ? 3 : 2);
         hipFuncAttributes attr;
         PMS_HIP(hipFuncGetAttributes(&attr, fn));
         const int vgprs = std::max(attr.numRegs, 8);
         const int per_simd = std::max(1, std::min(8, 512 / ((vgprs + 7) / 8 * 8)));
         const size_t budget = c.lds_per_cu / (4 * static_cast<size_t>(per_simd));
-        const size_t fit = budget / 4 > PMS_OUTBUF ? (budget / 4 - PMS_OUTBUF) / (entry * PMS_QCAP) : 0;
+        const size_t fit = budget / 4 > PMS_OUTBUF ? (budget / 4 - PMS_OUTBUF) / entry : 0;
         lds_stages = std::min<uint32_t>(stages, static_cast<uint32_t>(fit));
-        gq_words = (stages - lds_stages) * entry * PMS_QCAP;
-        per_wave = static_cast<size_t>(lds_stages * entry * PMS_QCAP + PMS_OUTBUF) * 4;
+        gq_words = (stages - lds_stages) * entry;
+        per_wave = static_cast<size_t>(lds_stages * entry + PMS_OUTBUF) * 4;
     }
     uint32_t w = cfg.wg_waves;
     if (variant == PMS_VARIANT_GROUP64) w = std::min<uint32_t>(w, PMS_GROUP64_MAX_THREADS / 64);
@@ -709,6 +709,13 @@ void sort_codes(uint32_t* v, size_t k, int bits, std::vector<uint32_t>& tmp) {
     if (src != v) memcpy(v, src, k * 4);
 }
 
+// Candidate scan slots of a launch: 64 lanes x candidates per lane per
+// batch; GROUP64's single-candidate batches hold one candidate per lane.
+uint64_t candidate_slots(const pms_dev_counters& ctr, uint32_t variant) {
+    const uint64_t singles = ctr.single_batches;
+    return (ctr.batches - singles) * 64u * pms::candidates_per_lane(variant) + singles * 64u;
+}
+
 bool use_graph_default() {
     const char* v = getenv("PMS_NO_GRAPH");
     return !(v && *v && *v != '0');
@@ -754,7 +761,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     c.last.seq_visits = visits;
     c.last.window_compares = wcmp;
     c.last.batches = ctr->batches;
-    c.last.candidate_slots = ctr->batches * 64u * pms::candidates_per_lane(b.variant);
+    c.last.candidate_slots = candidate_slots(*ctr, b.variant);
     c.last.reruns = 0;
     // Step a7.  Every instance's codes go to its segment of one pinned
     // buffer: asynchronous copies, one synchronisation.  Outputs larger than
@@ -1256,7 +1263,7 @@ int pms_last_stats(pms_stats* out) {
             c.last.seq_visits = st.visits;
             c.last.window_compares = st.visits * static_cast<uint64_t>(c.dv_nw);
             c.last.batches = ctr.batches;
-            c.last.candidate_slots = ctr.batches * 64u * pms::candidates_per_lane(c.dv_variant);
+            c.last.candidate_slots = candidate_slots(ctr, c.dv_variant);
         }
         c.last_pending = false;
     }

@@ -302,11 +302,80 @@ __device__ __forceinline__ typename MaskOf<S>::type scan_group_any(
     }
 }
 
+// One sequence scan for one candidate per lane: whether some window is
+// within d of the l-mer `code` (motif code).  All L positions are counted
+// per lane by the carry-save tree of scan_group, with no selection tree; the
+// bias is 15 - d, so c' = c + 15 - d < 32 and [c <= d] is ~c'16.  Used for
+// the live members of groups that have few left: per 32 windows it costs
+// about a third of a group scan.
+template <int L>
+__device__ __forceinline__ bool scan_single(cu32* W, uint32_t groups, uint32_t code, int d) {
+    uint32_t ch[L], cl[L];
+#pragma unroll
+    for (int p = 0; p < L; ++p) {
+        const uint32_t b = (code >> (2 * (L - 1 - p))) & 3u;
+        ch[p] = 0u - (b >> 1);
+        cl[p] = 0u - (b & 1u);
+    }
+    const uint32_t bias_value = static_cast<uint32_t>(15 - d);
+    uint32_t bias[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) bias[i] = to_vgpr(0u - ((bias_value >> i) & 1u));
+    uint32_t found = 0u;
+    uint32_t w[2 * L];
+#pragma unroll
+    for (int i = 0; i < 2 * L; ++i) w[i] = ((__attribute__((address_space(4))) const volatile uint32_t*)W)[i];
+    for (uint32_t gi = 0; gi < groups; ++gi) {
+        uint32_t m[L];
+#pragma unroll
+        for (int p = 0; p < L; ++p) m[p] = (w[p] ^ ch[p]) | (w[L + p] ^ cl[p]);
+        // The mismatch vectors are complete here: the next group's words
+        // load while they are counted.
+#pragma unroll
+        for (int p = 0; p < L; ++p) asm volatile("" : "+v"(m[p]));
+        W += gi + 1 < groups ? 2 * L : 0;
+        asm volatile("" : "+s"(W));
+#pragma unroll
+        for (int i = 0; i < 2 * L; ++i) w[i] = W[i];
+        uint32_t c[5];
+        count_bits<L>(m, bias, c);
+        found |= ~c[4];
+    }
+    return found != 0u;
+}
+
+// Dispatch on l (wave-uniform, 3 <= l <= 16).  d >= l: every window is
+// within d.
+__device__ __forceinline__ bool scan_single_any(uint32_t L, cu32* W, uint32_t groups, uint32_t code,
+                                                int d) {
+    if (d >= static_cast<int>(L)) return true;
+    switch (L) {
+        case 3: return scan_single<3>(W, groups, code, d);
+        case 4: return scan_single<4>(W, groups, code, d);
+        case 5: return scan_single<5>(W, groups, code, d);
+        case 6: return scan_single<6>(W, groups, code, d);
+        case 7: return scan_single<7>(W, groups, code, d);
+        case 8: return scan_single<8>(W, groups, code, d);
+        case 9: return scan_single<9>(W, groups, code, d);
+        case 10: return scan_single<10>(W, groups, code, d);
+        case 11: return scan_single<11>(W, groups, code, d);
+        case 12: return scan_single<12>(W, groups, code, d);
+        case 13: return scan_single<13>(W, groups, code, d);
+        case 14: return scan_single<14>(W, groups, code, d);
+        case 15: return scan_single<15>(W, groups, code, d);
+        default: return scan_single<16>(W, groups, code, d);
+    }
+}
+
 // Persistent grouped search; S = 2 (16 candidates per lane) or 3 (64).
-// Stage queues for stages 1..lds_stages live in LDS; deeper stages (rarely
-// reached, so rarely touched) live in a per-wavefront region of the global
-// workspace `gq` (gq_words words per wavefront), which leaves room in LDS for
-// more resident wavefronts.
+// Per stage s = 1..n-1 a wavefront has a queue of groups (prefix and alive
+// mask) and, for S = 3, a queue of single candidates (motif codes): a group
+// that keeps at most kSparse live members after a sequence hands them on as
+// singles, which cost a fraction of a group scan.  Stage queues for stages
+// 1..lds_stages live in LDS; deeper stages live in a per-wavefront region of
+// the global workspace `gq` (gq_words words per wavefront), which leaves room
+// in LDS for more resident wavefronts.  Per stage, in both places: group
+// prefixes [QCAP] u32, masks [QCAP] Mask, then (S = 3) singles [SCAP] u32.
 template <int S>
 __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict__ insts,
                                               const pms_work_item* __restrict__ work,
@@ -319,27 +388,27 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     constexpr uint32_t kNone = 0xffffffffu;
     constexpr Mask kAll = static_cast<Mask>(~static_cast<Mask>(0)) >> (8 * sizeof(Mask) - K);
     constexpr uint32_t kEntryWords = 1 + sizeof(Mask) / 4;
+    constexpr bool kSingles = S == 3;
+    constexpr uint32_t kSparse = 2;   // a group with at most this many live members splits
+    constexpr uint32_t kStageWords = pms::stage_queue_words(S);
+    constexpr uint32_t kSingleOff = kEntryWords * PMS_QCAP;
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
     const uint32_t wave = uni(threadIdx.x >> 6);
-    // Per wavefront in LDS: queue prefixes [lds_stages][QCAP] u32, masks
-    // [lds_stages][QCAP] Mask, survivor staging [OUTBUF] u32.  In the
-    // workspace: per deeper stage, prefixes [QCAP] u32 then masks [QCAP] Mask.
-    const uint32_t q_words = lds_stages * kEntryWords * PMS_QCAP;
-    uint32_t* const qp = lds + wave * (q_words + PMS_OUTBUF);
-    Mask* const qm = reinterpret_cast<Mask*>(qp + lds_stages * PMS_QCAP);
-    uint32_t* const ob = qp + q_words;
+    uint32_t* const qp = lds + wave * (lds_stages * kStageWords + PMS_OUTBUF);
+    uint32_t* const ob = qp + lds_stages * kStageWords;
     const uint32_t gwave = blockIdx.x * uni(blockDim.x >> 6) + wave;
     uint32_t* const gw = gq + static_cast<size_t>(gwave) * gq_words;
-    const uint32_t stages_cap = lds_stages + gq_words / (kEntryWords * PMS_QCAP);
+    const uint32_t stages_cap = lds_stages + gq_words / kStageWords;
 
     uint32_t cur = kNone, pending = 0, stash = kNone;
     bool more = true;
     uint64_t next = 0, end = 0;     // group numbers
-    uint64_t batches = 0;
+    uint64_t batches = 0, single_batches = 0;
     uint64_t visits = 0;            // per lane
     uint32_t nob = 0;
-    uint32_t counts = 0;            // lane s: groups queued for stage s
+    // Lane s: groups queued for stage s (low 16 bits) and singles (high 16).
+    uint32_t qc = 0;
 
     cu32* W = nullptr;
     uint32_t* out = nullptr;
@@ -348,24 +417,44 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     int d = 0;
 
     for (;;) {
+        // prefix: a group's prefix, or a single's motif code.
         uint32_t s, prefix = 0;
         Mask alive = 0;
-        const uint64_t full = ballot(counts >= 64u);
-        if (full) {
-            s = 63u - static_cast<uint32_t>(__builtin_clzll(full));
-            const uint32_t c = __builtin_amdgcn_readlane(counts, s);
-            const uint32_t at = c - 64u + lane;
-            const uint32_t row = s - 1;
-            if (row < lds_stages) {
-                prefix = qp[row * PMS_QCAP + at];
-                alive = qm[row * PMS_QCAP + at];
+        bool single = false;
+        const uint64_t full = ballot((qc & 0xffffu) >= 64u);
+        const uint64_t sfull = kSingles ? ballot(qc >= (64u << 16)) : 0;
+        if (full | sfull) {
+            // The deepest full queue: at most one queue is ever full, and
+            // scanning it pushes no more than 64 groups, or 64 singles, or
+            // as many singles as fit, onto the next stage's queues.
+            const int sg = full ? 63 - __builtin_clzll(full) : -1;
+            const int ss = sfull ? 63 - __builtin_clzll(sfull) : -1;
+            single = ss > sg;
+            s = static_cast<uint32_t>(single ? ss : sg);
+            const uint32_t cw = __builtin_amdgcn_readlane(qc, s);
+            const uint32_t at = (single ? cw >> 16 : cw & 0xffffu) - 64u + lane;
+            const uint32_t r = s - 1;
+            if (r < lds_stages) {
+                const uint32_t* q = qp + r * kStageWords;
+                if (single) {
+                    prefix = q[kSingleOff + at];
+                    alive = 1;
+                } else {
+                    prefix = q[at];
+                    alive = reinterpret_cast<const Mask*>(q + PMS_QCAP)[at];
+                }
             } else {
-                const uint32_t* g = gw + (row - lds_stages) * kEntryWords * PMS_QCAP;
+                const uint32_t* g = gw + (r - lds_stages) * kStageWords;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                prefix = g[at];
-                alive = reinterpret_cast<const Mask*>(g + PMS_QCAP)[at];
+                if (single) {
+                    prefix = g[kSingleOff + at];
+                    alive = 1;
+                } else {
+                    prefix = g[at];
+                    alive = reinterpret_cast<const Mask*>(g + PMS_QCAP)[at];
+                }
             }
-            if (lane == s) counts -= 64u;
+            if (lane == s) qc -= single ? (64u << 16) : 64u;
         } else if (next < end) {
             s = 0;
             const uint64_t g = next + lane;
@@ -392,8 +481,9 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 }
                 continue;
             }
-            const uint64_t nz = ballot(counts > 0u);
-            if (nz == 0) {
+            const uint64_t nz = ballot((qc & 0xffffu) > 0u);
+            const uint64_t snz = kSingles ? ballot(qc > 0xffffu) : 0;
+            if ((nz | snz) == 0) {
                 if (cur != kNone) {
                     if (nob) {
                         uint64_t base = 0;
@@ -441,23 +531,78 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 end = (wi.begin + wi.len) >> (2 * S);
                 continue;
             }
-            s = static_cast<uint32_t>(__builtin_ctzll(nz));
-            const uint32_t c = __builtin_amdgcn_readlane(counts, s);
-            const uint32_t row = s - 1;
-            if (row < lds_stages) {
+            // No queue is full and no new work: drain the shallowest queue.
+            const int sg = nz ? __builtin_ctzll(nz) : 64;
+            const int ss = snz ? __builtin_ctzll(snz) : 64;
+            single = ss < sg;
+            s = static_cast<uint32_t>(single ? ss : sg);
+            const uint32_t cw = __builtin_amdgcn_readlane(qc, s);
+            const uint32_t c = single ? cw >> 16 : cw & 0xffffu;
+            const uint32_t r = s - 1;
+            if (r < lds_stages) {
+                const uint32_t* q = qp + r * kStageWords;
                 if (lane < c) {
-                    prefix = qp[row * PMS_QCAP + lane];
-                    alive = qm[row * PMS_QCAP + lane];
+                    if (single) {
+                        prefix = q[kSingleOff + lane];
+                        alive = 1;
+                    } else {
+                        prefix = q[lane];
+                        alive = reinterpret_cast<const Mask*>(q + PMS_QCAP)[lane];
+                    }
                 }
             } else {
-                const uint32_t* g = gw + (row - lds_stages) * kEntryWords * PMS_QCAP;
+                const uint32_t* g = gw + (r - lds_stages) * kStageWords;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 if (lane < c) {
-                    prefix = g[lane];
-                    alive = reinterpret_cast<const Mask*>(g + PMS_QCAP)[lane];
+                    if (single) {
+                        prefix = g[kSingleOff + lane];
+                        alive = 1;
+                    } else {
+                        prefix = g[lane];
+                        alive = reinterpret_cast<const Mask*>(g + PMS_QCAP)[lane];
+                    }
                 }
             }
-            if (lane == s) counts = 0;
+            if (lane == s) qc &= single ? 0xffffu : 0xffff0000u;
+        }
+
+        if (kSingles && single) {
+            // One sequence scan for up to 64 single candidates.
+            const bool live = alive != 0;
+            const bool ok = live && scan_single_any(P + S, W + s * row, groups, prefix, d);
+            visits += live ? 1u : 0u;
+            ++batches;
+            ++single_batches;
+            const uint64_t pm = ballot(ok);
+            if (pm) {
+                const uint32_t rk = rank_below(pm);
+                if (s + 1 < n) {
+                    const uint32_t base = __builtin_amdgcn_readlane(qc, s + 1) >> 16;
+                    const uint32_t r = s;
+                    if (r < lds_stages) {
+                        if (ok) qp[r * kStageWords + kSingleOff + base + rk] = prefix;
+                    } else {
+                        uint32_t* g = gw + (r - lds_stages) * kStageWords;
+                        if (ok) g[kSingleOff + base + rk] = prefix;
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    }
+                    if (lane == s + 1) qc += static_cast<uint32_t>(__builtin_popcountll(pm)) << 16;
+                } else {
+                    if (ok) ob[nob + rk] = prefix;
+                    nob += static_cast<uint32_t>(__builtin_popcountll(pm));
+                    if (nob > PMS_OUTBUF - 64u) {
+                        uint64_t base = 0;
+                        if (lane == 0)
+                            base = atomicAdd(reinterpret_cast<unsigned long long*>(&state[cur].count),
+                                             static_cast<unsigned long long>(nob));
+                        base = uni64(base);
+                        for (uint32_t i = lane; i < nob; i += 64u)
+                            if (base + i < cap) out[base + i] = ob[i];
+                        nob = 0;
+                    }
+                }
+            }
+            continue;
         }
 
         // One sequence scan for 64 groups.
@@ -468,23 +613,90 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         const uint64_t pm = ballot(keep);
         if (pm) {
             if (s + 1 < n) {
-                const uint32_t base = __builtin_amdgcn_readlane(counts, s + 1);
-                const uint32_t r = rank_below(pm);
-                const uint32_t row = s;
-                if (row < lds_stages) {
-                    if (keep) {
-                        qp[row * PMS_QCAP + base + r] = prefix;
-                        qm[row * PMS_QCAP + base + r] = pass;
+                const uint32_t live = static_cast<uint32_t>(__builtin_popcountll(static_cast<uint64_t>(pass)));
+                const bool sparse = kSingles && keep && live <= kSparse;
+                const uint64_t dm = kSingles ? ballot(keep && !sparse) : pm;
+                const uint32_t r = s;
+                if (dm) {
+                    const uint32_t base = __builtin_amdgcn_readlane(qc, s + 1) & 0xffffu;
+                    const uint32_t rk = rank_below(dm);
+                    const bool dense = keep && !sparse;
+                    if (r < lds_stages) {
+                        uint32_t* q = qp + r * kStageWords;
+                        if (dense) {
+                            q[base + rk] = prefix;
+                            reinterpret_cast<Mask*>(q + PMS_QCAP)[base + rk] = pass;
+                        }
+                    } else {
+                        uint32_t* g = gw + (r - lds_stages) * kStageWords;
+                        if (dense) {
+                            g[base + rk] = prefix;
+                            reinterpret_cast<Mask*>(g + PMS_QCAP)[base + rk] = pass;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     }
-                } else {
-                    uint32_t* g = gw + (row - lds_stages) * kEntryWords * PMS_QCAP;
-                    if (keep) {
-                        g[base + r] = prefix;
-                        reinterpret_cast<Mask*>(g + PMS_QCAP)[base + r] = pass;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    if (lane == s + 1) qc += static_cast<uint32_t>(__builtin_popcountll(dm));
                 }
-                if (lane == s + 1) counts += static_cast<uint32_t>(__builtin_popcountll(pm));
+                if constexpr (kSingles) {
+                    // Sparse groups: their one or two live members as
+                    // singles, in lane order while the singles queue has
+                    // room; the rest (rarely any) go on as groups after all.
+                    const uint64_t b1 = ballot(sparse && live == 1u);
+                    const uint64_t b2 = ballot(sparse && live == 2u);
+                    if (b1 | b2) {
+                        const uint32_t sbase = __builtin_amdgcn_readlane(qc, s + 1) >> 16;
+                        const uint32_t at = sbase + rank_below(b1) + 2u * rank_below(b2);
+                        uint32_t total = static_cast<uint32_t>(__builtin_popcountll(b1) + 2 * __builtin_popcountll(b2));
+                        bool fits = sparse;
+                        uint64_t over = 0;
+                        if (sbase + total > PMS_SCAP) {
+                            fits = sparse && at + live <= PMS_SCAP;
+                            over = ballot(sparse && !fits);
+                            total = static_cast<uint32_t>(__builtin_popcountll(ballot(fits && live == 1u)) +
+                                                          2 * __builtin_popcountll(ballot(fits && live == 2u)));
+                        }
+                        const uint64_t pw = static_cast<uint64_t>(pass);
+                        const uint32_t lo = (prefix << (2 * S)) | static_cast<uint32_t>(__builtin_ctzll(pw));
+                        const uint32_t hi = (prefix << (2 * S)) | static_cast<uint32_t>(63 - __builtin_clzll(pw));
+                        if (r < lds_stages) {
+                            uint32_t* q = qp + r * kStageWords + kSingleOff;
+                            if (fits) {
+                                q[at] = lo;
+                                if (live == 2u) q[at + 1] = hi;
+                            }
+                        } else {
+                            uint32_t* g = gw + (r - lds_stages) * kStageWords + kSingleOff;
+                            if (fits) {
+                                g[at] = lo;
+                                if (live == 2u) g[at + 1] = hi;
+                            }
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                        }
+                        if (lane == s + 1) qc += total << 16;
+                        if (over) {
+                            // Groups whose members did not fit: group queue
+                            // (with the dense ones, at most 64 pushed).
+                            const uint32_t base = __builtin_amdgcn_readlane(qc, s + 1) & 0xffffu;
+                            const uint32_t rk = rank_below(over);
+                            const bool push = sparse && !fits;
+                            if (r < lds_stages) {
+                                uint32_t* q = qp + r * kStageWords;
+                                if (push) {
+                                    q[base + rk] = prefix;
+                                    reinterpret_cast<Mask*>(q + PMS_QCAP)[base + rk] = pass;
+                                }
+                            } else {
+                                uint32_t* g = gw + (r - lds_stages) * kStageWords;
+                                if (push) {
+                                    g[base + rk] = prefix;
+                                    reinterpret_cast<Mask*>(g + PMS_QCAP)[base + rk] = pass;
+                                }
+                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                            }
+                            if (lane == s + 1) qc += static_cast<uint32_t>(__builtin_popcountll(over));
+                        }
+                    }
+                }
             } else {
                 // Survivors: each lane writes its alive candidates in turn;
                 // every round compacts one code per lane by ballot.
@@ -513,9 +725,13 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             }
         }
     }
-    if (lane == 0)
+    if (lane == 0) {
         atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->batches),
                   static_cast<unsigned long long>(batches));
+        if (single_batches)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->single_batches),
+                      static_cast<unsigned long long>(single_batches));
+    }
 }
 
 }  // namespace
@@ -546,9 +762,8 @@ hipError_t launch_search_group(const pms_dev_instance* insts, const pms_work_ite
                                uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
                                const GroupQueues& q, uint32_t grid, uint32_t wg_waves,
                                hipStream_t stream, int suffix) {
-    const uint32_t entry = suffix == 3 ? 3u : 2u;
     const size_t lds = static_cast<size_t>(wg_waves) *
-                       (q.lds_stages * entry * PMS_QCAP + PMS_OUTBUF) * sizeof(uint32_t);
+                       (q.lds_stages * stage_queue_words(suffix) + PMS_OUTBUF) * sizeof(uint32_t);
     if (suffix == 3)
         hipLaunchKernelGGL(pms_search_group64_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream,
                            insts, work, n_work, state, ctr, q.lds_stages, q.gq, q.gq_words);

@@ -11,6 +11,10 @@
 // ever at or above 64 entries and it is scanned before anything else is
 // pushed, so every queue stays below 128.
 #define PMS_QCAP 128u
+// Single-candidate queue slots per stage (64-candidate kernel).  A singles
+// scan pushes at most 64 onto a queue below 64; a group scan pushes sparse
+// groups' members only while they fit.
+#define PMS_SCAP 128u
 // Per-wavefront staging slots for final survivors (flushed at > OUTBUF-64).
 #define PMS_OUTBUF 256u
 // Largest workgroup of the 64-candidates-per-lane kernel (4 wavefronts).
@@ -74,13 +78,22 @@ const void* search_group_kernel_symbol(int suffix);
 hipError_t valu_probe(int op, uint32_t blocks, uint32_t iters, uint32_t* sink, uint64_t* clocks,
                       hipStream_t s);
 
-// LDS words of stage queues one wavefront needs for instances of up to
-// max_n sequences.  variant: LANE keeps one uint32 candidate per slot, GROUP
-// a uint32 prefix and a uint32 alive mask, GROUP64 a prefix and a uint64 mask.
+// Words of one stage's queues per wavefront in the grouped kernels: suffix
+// 2 keeps a uint32 prefix and a uint32 alive mask per group; suffix 3 a
+// prefix and a uint64 mask per group, then PMS_SCAP single motif codes.
+constexpr uint32_t stage_queue_words(int suffix) {
+    return suffix == 3 ? 3u * PMS_QCAP + PMS_SCAP : 2u * PMS_QCAP;
+}
+
+// Words of stage queues one wavefront needs for instances of up to max_n
+// sequences.  variant: LANE keeps one uint32 candidate per slot; the grouped
+// variants as in stage_queue_words.
 inline uint32_t queue_words(int32_t max_n, uint32_t variant) {
     const uint32_t stages = static_cast<uint32_t>(max_n > 1 ? max_n - 1 : 0);
-    const uint32_t words = variant == PMS_VARIANT_GROUP64 ? 3u : variant == PMS_VARIANT_GROUP ? 2u : 1u;
-    return stages * words * PMS_QCAP;
+    const uint32_t words = variant == PMS_VARIANT_GROUP64 ? stage_queue_words(3)
+                           : variant == PMS_VARIANT_GROUP ? stage_queue_words(2)
+                                                          : PMS_QCAP;
+    return stages * words;
 }
 
 // Candidates per lane of a variant.

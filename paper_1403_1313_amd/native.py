@@ -44,6 +44,22 @@ class Result(ctypes.Structure):
                 ("count", ctypes.c_uint64), ("latency_ms", ctypes.c_double)]
 
 
+def _record_dtype(struct) -> np.dtype:
+    """The numpy record layout of a ctypes structure (same offsets and size),
+    so that arrays of them can be filled and read without per-field calls."""
+    kinds = {ctypes.c_int32: np.int32, ctypes.c_uint64: np.uint64, ctypes.c_double: np.float64}
+    names, formats, offsets = [], [], []
+    for name, ct in struct._fields_:
+        names.append(name)
+        formats.append(kinds.get(ct, np.uint64))   # pointers as addresses
+        offsets.append(getattr(struct, name).offset)
+    return np.dtype({"names": names, "formats": formats, "offsets": offsets,
+                     "itemsize": ctypes.sizeof(struct)})
+
+
+_INSTANCE_DT = _record_dtype(Instance)
+_RESULT_DT = _record_dtype(Result)
+
 VARIANT_AUTO, VARIANT_LANE, VARIANT_GROUP, VARIANT_GROUP64 = 0, 1, 2, 3
 INPUT_MASK_N, INPUT_BOTH_STRANDS = 1, 2
 VARIANT_NAMES = {1: "lane", 2: "group16", 3: "group64"}
@@ -96,7 +112,8 @@ class DevState(ctypes.Structure):
 
 class DevCounters(ctypes.Structure):
     _fields_ = [("next_item", ctypes.c_uint32), ("error", ctypes.c_uint32),
-                ("batches", ctypes.c_uint64), ("t_start", ctypes.c_uint64)]
+                ("batches", ctypes.c_uint64), ("t_start", ctypes.c_uint64),
+                ("single_batches", ctypes.c_uint64)]
 
 
 def _load():
@@ -275,30 +292,41 @@ def solve_intersect(seqs, l: int, d: int) -> np.ndarray:
     return res
 
 
+def _row_pointers(seqs):
+    """(address of n row pointers, object keeping them alive, n, t)."""
+    if isinstance(seqs, np.ndarray):
+        m = np.ascontiguousarray(seqs, dtype=np.uint8)
+        if m.ndim != 2:
+            raise ValueError("sequence array must be 2-D (n, t)")
+        n, t = int(m.shape[0]), int(m.shape[1])
+        ptrs = m.ctypes.data + np.arange(max(n, 1), dtype=np.uint64) * np.uint64(t)
+        return ptrs.ctypes.data, (m, ptrs), n, t
+    arr, rows, n, t = _rows(seqs)
+    return ctypes.addressof(arr), (arr, rows), n, t
+
+
 def solve_many(instances: Sequence[Tuple[object, int, int]], capacities=None):
     """pms_solve_many over [(seqs, l, d), ...]: (status, [motifs], [Result])."""
     m = len(instances)
-    insts = (Instance * max(m, 1))()
-    caps = [(1 << 16) if capacities is None else int(capacities[i]) for i in range(m)]
-    pool = _out_buffer(sum(max(c, 1) for c in caps))
-    keep, outs = [], []
-    off = 0
+    caps = (np.full(m, 1 << 16, dtype=np.uint64) if capacities is None
+            else np.asarray([int(c) for c in capacities[:m]], dtype=np.uint64))
+    offs = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.maximum(caps, 1).astype(np.int64), out=offs[1:])
+    pool = _out_buffer(int(offs[m]))
+    base = pool.ctypes.data
+    rec = np.zeros(max(m, 1), dtype=_INSTANCE_DT)
+    keep = []
     for i, (seqs, l, d) in enumerate(instances):
-        arr, rows, n, t = _rows(seqs)
-        cap = caps[i]
-        out = pool[off:off + max(cap, 1)]
-        off += max(cap, 1)
-        keep.append((arr, rows))
-        outs.append(out)
-        insts[i].seqs = ctypes.cast(arr, ctypes.POINTER(ctypes.c_char_p))
-        insts[i].n, insts[i].t, insts[i].l, insts[i].d = n, t, l, d
-        insts[i].out_motifs = out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if cap else None
-        insts[i].capacity = cap
+        addr, k, n, t = _row_pointers(seqs)
+        keep.append(k)
+        rec[i] = (addr, n, t, l, d, base + 4 * int(offs[i]) if caps[i] else 0, caps[i])
     res = (Result * max(m, 1))()
-    st = _lib.pms_solve_many(insts, m, res)
-    results = [res[i] for i in range(m)]
-    motifs = [outs[i][:min(int(results[i].count), len(outs[i]))].copy() for i in range(m)]
-    return st, motifs, results
+    st = _lib.pms_solve_many(ctypes.cast(rec.ctypes.data, ctypes.POINTER(Instance)), m, res)
+    del keep
+    counts = np.frombuffer(res, dtype=_RESULT_DT, count=m)["count"]
+    take = np.minimum(counts, caps).astype(np.int64)
+    motifs = [pool[offs[i]:offs[i] + take[i]].copy() for i in range(m)]
+    return st, motifs, [res[i] for i in range(m)]
 
 
 def decode(code: int, l: int) -> str:

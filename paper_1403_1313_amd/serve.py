@@ -21,6 +21,7 @@ computation runs in the library's kernels.
 from __future__ import annotations
 
 import collections
+import ctypes
 import concurrent.futures as cf
 import dataclasses
 import math
@@ -99,7 +100,7 @@ class _StepBuf:
         self.max_items = max_items
         self.h_work = torch.zeros(max_items * 16, dtype=torch.uint8).pin_memory()
         self.d_work = torch.zeros(max_items * 16, dtype=torch.uint8, device=dev)
-        self.d_ctr = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.d_ctr = torch.zeros(ctypes.sizeof(nat.DevCounters) // 8, dtype=torch.int64, device=dev)
         self.h_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8).pin_memory()
         self.event = None           # end of the search launch (timed)
         self.done = None            # state snapshot copied to the host
