@@ -137,17 +137,21 @@ def bench_serving(args):
     from . import native as nat
     from .serve import Server
 
-    rates = [float(r) for r in os.environ.get("PMS_SERVE_RATES", "20,200,1000").split(",")]
+    rates = [float(r) for r in os.environ.get("PMS_SERVE_RATES", "20,200,1000,1500").split(",")]
     fixed = os.environ.get("PMS_SERVE_COUNT")
     step_ms = float(os.environ.get("PMS_SERVE_STEP_MS", "2.0"))
     oldest = float(os.environ.get("PMS_SERVE_OLDEST_SHARE", "0.5"))
+    inflight = int(os.environ.get("PMS_SERVE_INFLIGHT", "2"))
+    min_step = os.environ.get("PMS_SERVE_MIN_STEP_MS")
+    min_step = float(min_step) if min_step else step_ms / 2
     out = []
     for rate in rates:
         # about a second of arrivals, at least 60 and at most 300 requests
         count = int(fixed) if fixed else int(min(300, max(60, rate)))
         stream = fmgen.serving_stream(count, rate)
         reqs = [(t_arr, spec.make()) for t_arr, spec in stream]
-        with Server(mem_budget=256 << 20, step_ms=step_ms, oldest_share=oldest) as srv:
+        with Server(mem_budget=256 << 20, step_ms=step_ms, oldest_share=oldest,
+                    max_inflight=inflight, min_step_ms=min_step) as srv:
             # warm up the kernels and allocator
             srv.submit(reqs[0][1].seqs, reqs[0][1].l, reqs[0][1].d).result()
             t0 = time.perf_counter()
@@ -188,7 +192,7 @@ def bench_serving(args):
                                "(9,2),(11,3),(13,4),(15,4) weighted 4:3:2:1, n in [10,30], "
                                "t in [300,1000], master seed 1313", "rates": rates,
                    "requests": [r["requests"] for r in out], "step_ms": step_ms,
-                   "oldest_share": oldest},
+                   "oldest_share": oldest, "max_inflight": inflight, "min_step_ms": min_step},
         "sweep": out,
     }
     print(json.dumps(line), flush=True)

@@ -35,6 +35,7 @@ from . import native as nat
 
 MAX_SLOTS = 1024
 ITEMS_UNTRACKED = 1 << 31  # serving does not use per-instance completion stamps
+EAGER_CODES = 1 << 16      # codes copied back right after a request's last step
 
 
 def _estimate(l: int, d: int, n: int, t: int):
@@ -66,7 +67,7 @@ class Result:
 class _Req:
     __slots__ = ("rid", "seqs", "l", "d", "n", "t", "arrival", "future", "slot", "dev_seqs",
                  "dev_win", "dev_out", "cap", "bytes", "total", "cursor", "inflight", "steps",
-                 "reruns", "admitted", "cost_per_cand", "stride")
+                 "reruns", "admitted", "cost_per_cand", "stride", "h_out")
 
     def __init__(self, rid, seqs, l, d, arrival, future):
         self.rid = rid
@@ -87,6 +88,7 @@ class _Req:
         self.steps = 0
         self.reruns = 0
         self.admitted = 0.0
+        self.h_out = None   # pinned copy of the first codes, made right after the last step
         self.bytes = self._bytes()
 
     def _bytes(self) -> int:
@@ -117,7 +119,8 @@ class Server:
     def __init__(self, mem_budget: int = 256 << 20, step_ms: float = 2.0,
                  max_inflight: int = 2, compares_per_s: float = 2.5e14,
                  device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
-                 items_per_step: int = 8192, oldest_share: float = 0.5):
+                 items_per_step: int = 8192, oldest_share: float = 0.5,
+                 min_step_ms: Optional[float] = None, backlog_share: float = 0.25):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)
@@ -126,7 +129,13 @@ class Server:
         self.mem_budget = int(mem_budget)
         # Steps are sized in estimated window compares; the rate starts at
         # compares_per_s and follows the measured device time of each step.
+        # A step holds backlog_share of the admitted work left, between
+        # min_step_ms (default step_ms / 2) and step_ms of device time: short
+        # steps let new requests in sooner, long ones cost fewer fixed
+        # per-step costs when there is a backlog to clear.
         self.step_s = step_ms * 1e-3
+        self.min_step_s = (step_ms / 2 if min_step_ms is None else min_step_ms) * 1e-3
+        self.backlog_share = float(backlog_share)
         self.rate = float(compares_per_s)
         self.step_compares = self.step_s * self.rate
         self.items_per_step = int(items_per_step)
@@ -143,6 +152,7 @@ class Server:
         self.bufs = [_StepBuf(torch, self.dev, 2 * self.items_per_step) for _ in range(max_inflight)]
         self.idle_bufs = list(self.bufs)
         self.inflight: Deque[_StepBuf] = collections.deque()
+        self.finishing: Deque[tuple] = collections.deque()   # codes on their way to the host
         self.waiting: Deque[_Req] = collections.deque()
         self.active: List[_Req] = []
         self.mem_used = 0
@@ -254,8 +264,9 @@ class Server:
     def _build_step(self, buf: _StepBuf) -> int:
         """Fills one step's work table up to the step budget.
 
-        Shortest remaining work first (it minimises the mean latency), except
-        that the oldest admitted request is always given half of the step
+        Shortest remaining work first for requests that fit in one step (it
+        minimises the mean latency), then the longer requests in arrival
+        order; the oldest admitted request is always given half of the step
         so that a long request is never starved by a stream of short ones.
         Shares are cut into items of about ``step_compares / items_per_step``
         window compares each, so every step offers a few items per resident
@@ -265,13 +276,31 @@ class Server:
         if not live:
             return 0
         buf.compares = 0.0
-        budget = self.step_compares
+        backlog = sum((r.total - r.cursor) * r.cost_per_cand for r in live)
+        budget = min(max(self.backlog_share * backlog, self.min_step_s * self.rate), self.step_compares)
+        if len(live) == 1 and not self.waiting:
+            # Nothing to share the device with: one step takes all of it.
+            budget = max(budget, backlog)
         buf.budget = budget
         oldest = min(live, key=lambda r: r.arrival)
         order = sorted(live, key=lambda r: (r.total - r.cursor) * r.cost_per_cand)
         shares = {oldest.rid: self.oldest_share * budget}
         left = (1.0 - self.oldest_share) * budget
+        # Requests that fit in one step, shortest first; what is left goes to
+        # the longer ones in arrival order, so that two long requests run one
+        # after the other instead of both finishing late.
+        longer = []
         for r in order:
+            want = (r.total - r.cursor) * r.cost_per_cand - shares.get(r.rid, 0.0)
+            if want > budget:
+                longer.append(r)
+                continue
+            give = min(max(want, 0.0), left)
+            shares[r.rid] = shares.get(r.rid, 0.0) + give
+            left -= give
+        for r in sorted(longer, key=lambda r: r.arrival):
+            if left <= 0:
+                break
             want = (r.total - r.cursor) * r.cost_per_cand - shares.get(r.rid, 0.0)
             give = min(max(want, 0.0), left)
             shares[r.rid] = shares.get(r.rid, 0.0) + give
@@ -340,6 +369,16 @@ class Server:
             buf.event = torch.cuda.Event(enable_timing=True)
             buf.event.record(self.stream)
             buf.h_state.copy_(self.d_state, non_blocking=True)
+            # Requests whose last candidates are in this step: their first
+            # codes come back on this stream, before the next step's kernel
+            # takes every compute unit (a copy queued behind it would wait
+            # a whole step).  The count is known only at retirement; more
+            # codes than were copied take the side-stream path.
+            for r in buf.reqs:
+                if EAGER_CODES and r.cursor >= r.total:
+                    k = min(r.cap, EAGER_CODES)
+                    r.h_out = torch.empty(k, dtype=torch.int32, pin_memory=True)
+                    r.h_out.copy_(r.dev_out[:k], non_blocking=True)
             buf.done = torch.cuda.Event()
             buf.done.record(self.stream)
         for r in buf.reqs:
@@ -375,6 +414,7 @@ class Server:
         torch = self.torch
         if count > r.cap:
             # Reservation too small: run the request again with the exact size.
+            r.h_out = None
             self.mem_used -= r.bytes
             r.cap = count
             r.bytes = r._bytes()
@@ -385,46 +425,83 @@ class Server:
             self.stats["reruns"] += 1
             self._write_slot(r)
             return
-        # The request's last step has completed (done_event); copy on a side
-        # stream so the read does not wait for steps queued after it.
-        self.copy_stream.wait_event(done_event)
-        with torch.cuda.stream(self.copy_stream):
-            host = r.dev_out[:count].to("cpu", non_blocking=False) if count else None
-        codes = np.sort(host.numpy().view(np.uint32)) if count else np.zeros(0, dtype=np.uint32)
-        res = Result(codes, count, r.arrival, r.admitted, time.perf_counter(), r.steps, r.reruns,
-                     visits)
+        # The request's last step has completed (done_event).  Its codes are
+        # copied on a side stream, so the copy does not wait for steps queued
+        # after it, into pinned memory, asynchronously: the request completes
+        # in _complete once the copy's event has fired, and the loop goes on
+        # launching steps meanwhile.  Its slot is free now (no later step
+        # refers to it); its buffers stay referenced until the copy is done.
         self.active.remove(r)
-        self.mem_used -= r.bytes
         self.free_slots.append(r.slot)
+        if r.h_out is not None and count <= r.h_out.numel():
+            # The codes came back with the step (done_event has completed).
+            host = r.h_out[:count]
+            r.h_out = None
+            self._deliver(r, host, count, visits)
+            return
+        r.h_out = None
+        host = None
+        if count:
+            host = torch.empty(count, dtype=torch.int32, pin_memory=True)
+            self.copy_stream.wait_event(done_event)
+            with torch.cuda.stream(self.copy_stream):
+                host.copy_(r.dev_out[:count], non_blocking=True)
+        copied = torch.cuda.Event()
+        copied.record(self.copy_stream)
+        self.finishing.append((r, host, count, visits, copied))
+
+    def _complete(self, block: bool):
+        """Completes requests whose codes have reached the host, in order;
+        with block, waits for the first one."""
+        while self.finishing:
+            r, host, count, visits, copied = self.finishing[0]
+            if block:
+                copied.synchronize()
+                block = False
+            elif not copied.query():
+                return
+            self.finishing.popleft()
+            self._deliver(r, host, count, visits)
+
+    def _deliver(self, r: _Req, host, count: int, visits: int):
+        codes = np.sort(host.numpy().view(np.uint32)) if count else np.zeros(0, dtype=np.uint32)
+        res = Result(codes, count, r.arrival, r.admitted, time.perf_counter(), r.steps,
+                     r.reruns, visits)
+        self.mem_used -= r.bytes
         r.dev_seqs = r.dev_win = r.dev_out = None
         self.stats["completed"] += 1
         r.future.set_result(res)
 
     def _fail_all(self, exc: BaseException):
-        for r in list(self.active) + list(self.waiting):
+        for r in list(self.active) + list(self.waiting) + [f[0] for f in self.finishing]:
             if not r.future.done():
                 r.future.set_exception(exc)
         self.active.clear()
         self.waiting.clear()
+        self.finishing.clear()
 
     def _loop(self):
         try:
             while True:
                 with self.cv:
-                    if not self.running and not self.waiting and not self.active and not self.inflight:
+                    busy = self.waiting or self.active or self.inflight or self.finishing
+                    if not self.running and not busy:
                         return
-                    if not self.waiting and not self.active and not self.inflight:
+                    if not busy:
                         self.cv.wait(timeout=0.05)
                         continue
                     self._admit()
                 launched = False
                 while len(self.inflight) < self.max_inflight and self._launch():
                     launched = True
+                self._complete(block=False)
                 if self.inflight:
                     head = self.inflight[0]
                     if head.done.query() or not launched:
                         self.inflight.popleft()
                         self._retire(head)
+                elif self.finishing and not launched:
+                    self._complete(block=True)
         except BaseException as e:  # noqa: BLE001 - every request learns of the failure
             self.error = e
             with self.cv:
