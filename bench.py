@@ -74,6 +74,17 @@ def oracle_rate(seqs, l, d, mode, threads, seconds):
     return span / dt, span, dt
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(seqs, l, d, target_s):
     """The oracle (brute mode, unmodified) on a bounded prefix of the candidate
     space; beside it the oracle's skip mode (the paper's own CPU method,
@@ -99,6 +110,7 @@ def cpu_baseline(seqs, l, d, target_s):
     inst11 = fmgen.gen_fm(seed=0, **fmgen.PLAIN["plain_11_3"])
     one_rate, one_span, one_dt = oracle_rate(inst11.seqs, 11, 3, "skip", 1, 3.0)
     return {"value": span / dt, "unit": "candidates/s", "cores": threads, "kind": "oracle",
+            "host_cpu": host_cpu_model(), "host_threads_online": os.cpu_count(),
             "sample": f"brute-mode oracle over candidates [0, {span}) of the same instance "
                       f"({span / 4 ** l:.2e} of 4^{l}), {dt:.1f} s on {threads} host threads",
             "skip_mode": {"value": skip_rate, "unit": "candidates/s", "cores": threads,
@@ -158,13 +170,15 @@ def bench_plain(args):
     for _ in range(args.warmup):
         codes, st = step()
     torch.cuda.synchronize()
-    kernel_ms, windows_ms = [], []
+    kernel_ms, windows_ms, step_wall = [], [], []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
     w0 = time.perf_counter()
     for _ in range(args.steps):
+        s0 = time.perf_counter()
         codes, st = step()
+        step_wall.append(time.perf_counter() - s0)
         kernel_ms.append(st["kernel_ms"])
         windows_ms.append(st["windows_ms"])
     e1.record(stream)
@@ -215,6 +229,10 @@ def bench_plain(args):
                    "seed": args.seed, "candidates": cands},
         "window_compares_per_s": wc / (ms_step * 1e-3),
         "kernel_ms": k_ms,
+        "kernel_ms_median": float(np.median(kernel_ms)),
+        "kernel_ms_min": float(np.min(kernel_ms)),
+        "step_wall_ms_median": float(np.median(step_wall)) * 1e3,
+        "step_wall_ms_min": float(np.min(step_wall)) * 1e3,
         "windows_kernel_ms": float(np.mean(windows_ms)),
         "wall_ms_per_step": wall * 1e3 / args.steps,
         "seq_visits": st["seq_visits"],

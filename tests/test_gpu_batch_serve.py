@@ -182,3 +182,46 @@ def test_serving_rejects_invalid_requests(nat):
         assert np.array_equal(ok.motifs, oracle.solve(fmgen.random_seqs(3, 40, 2), 5, 1))
         one = srv.submit(fmgen.random_seqs(3, 40, 3), 1, 0).result(timeout=60)
         assert np.array_equal(one.motifs, oracle.solve(fmgen.random_seqs(3, 40, 3), 1, 0))
+
+
+def test_serving_large_outputs_and_their_order(nat):
+    """Outputs larger than the codes copied back with a request's last step
+    (d = l at l = 9 and 10: every l-mer; a radius-5 ball of 12-mers) come
+    back on the side stream; small requests submitted after them still
+    complete, each with its own set."""
+    from paper_1403_1313_amd.serve import EAGER_CODES, Server
+    big = [(fmgen.random_seqs(2, 12, 70), 9, 9), (fmgen.random_seqs(3, 15, 71), 10, 10),
+           (fmgen.random_seqs(1, 12, 72), 12, 5)]
+    small = mixed_batch()[:8]
+    want_small = oracle_sets(small)
+    want_ball = oracle.solve(big[2][0], 12, 5, mode="skip", cap=4 ** 12)
+    assert want_ball.size > EAGER_CODES
+    with Server(mem_budget=256 << 20, step_ms=0.5) as srv:
+        futs = [srv.submit(*b) for b in big] + [srv.submit(*b) for b in small]
+        got = [f.result(timeout=120) for f in futs]
+    assert np.array_equal(got[0].motifs, np.arange(4 ** 9, dtype=np.uint32))
+    assert np.array_equal(got[1].motifs, np.arange(4 ** 10, dtype=np.uint32))
+    assert np.array_equal(got[2].motifs, want_ball)
+    for g, w in zip(got[3:], want_small):
+        assert np.array_equal(g.motifs, w)
+
+
+def test_serving_burst_of_small_requests(nat):
+    """120 requests submitted at once: many share each step, each is exact."""
+    from paper_1403_1313_amd.serve import Server
+    rng = np.random.default_rng(123)
+    batch = []
+    for q in range(120):
+        l = int(rng.integers(4, 10))
+        d = int(rng.integers(0, min(2, l) + 1))
+        n = int(rng.integers(2, 9))
+        t = int(rng.integers(l, 120))
+        batch.append((fmgen.gen_fm(l, d, n, t, 4000 + q).seqs, l, d))
+    want = oracle_sets(batch)
+    with Server(mem_budget=256 << 20) as srv:
+        futs = [srv.submit(*b) for b in batch]
+        got = [f.result(timeout=120) for f in futs]
+        steps = srv.stats["steps"]
+    assert steps < len(batch)
+    for i, (g, w) in enumerate(zip(got, want)):
+        assert np.array_equal(g.motifs, w), i
