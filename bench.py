@@ -158,13 +158,19 @@ def bench_plain(args):
     out = torch.zeros(cap, dtype=torch.int32, device=dev)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
     host_cnt = torch.zeros(1, dtype=torch.int64).pin_memory()
+    # The count and the first codes come back in one round trip; a larger
+    # motif set takes a second copy.
+    head = 4096
+    host_out = torch.zeros(head, dtype=torch.int32).pin_memory()
 
     def step():
         nat.solve_dev(seqs, n, t, l, d, out, cap, cnt, stream=stream)
         host_cnt.copy_(cnt, non_blocking=True)
+        host_out.copy_(out[:head], non_blocking=True)
         stream.synchronize()
         k = min(int(host_cnt.item()), cap)
-        codes = np.sort(out[:k].cpu().numpy().view(np.uint32))
+        got = host_out[:k] if k <= head else out[:k].cpu()
+        codes = np.sort(got.numpy().view(np.uint32))
         return codes, nat.last_stats()
 
     for _ in range(args.warmup):

@@ -311,8 +311,8 @@ struct Ctx {
     std::string gsig;
     // device-level workspace for pms_solve_dev
     DevBuf dv_win, dv_meta, dv_gq;
-    HostBuf hv_meta;
-    hipEvent_t dv_copied = nullptr;
+    HostBuf hv_meta, hv_back;      // hv_back: state and counters copied after the launch
+    hipEvent_t dv_copied = nullptr, dv_back = nullptr;
     bool dv_copy_live = false;
     // where the last pms_solve_dev left its state and counters (0 = none)
     size_t dv_state_off = 0, dv_ctr_off = 0;
@@ -376,6 +376,7 @@ int init_ctx(Ctx& c) {
     PMS_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
     for (auto& e2 : c.ev) PMS_HIP(hipEventCreate(&e2));
     PMS_HIP(hipEventCreateWithFlags(&c.dv_copied, hipEventDisableTiming));
+    PMS_HIP(hipEventCreateWithFlags(&c.dv_back, hipEventDisableTiming));
     c.ready = true;
     return PMS_OK;
 }
@@ -528,19 +529,23 @@ void plan_batch(Batch& b, const pms_config& cfg, uint64_t target_items) {
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
     build_work(b, order, cost, cfg, target_items);
+    // Per-call records first (instances, then state, counters and bad-byte
+    // flags, which come back after the launch), then the plan's tables
+    // (window jobs, work items): a call that reuses a plan uploads
+    // [0, off_jobs) in one copy, and the results are [off_state, off_jobs).
     size_t off = 0;
     b.off_insts = off;
     off = align_up(off + m * sizeof(pms_dev_instance), 256);
-    b.off_jobs = off;
-    off = align_up(off + b.jobs.size() * sizeof(pms_win_job), 256);
-    b.off_work = off;
-    off = align_up(off + b.work.size() * sizeof(pms_work_item), 256);
     b.off_state = off;
     off = align_up(off + m * sizeof(pms_dev_state), 256);
     b.off_ctr = off;
     off = align_up(off + sizeof(pms_dev_counters), 256);
     b.off_bad = off;
     off = align_up(off + m * sizeof(uint32_t), 256);
+    b.off_jobs = off;
+    off = align_up(off + b.jobs.size() * sizeof(pms_win_job), 256);
+    b.off_work = off;
+    off = align_up(off + b.work.size() * sizeof(pms_work_item), 256);
     b.meta_bytes = off;
 }
 
@@ -609,7 +614,7 @@ int enqueue_batch(Ctx& c, const Batch& b, bool timed, const Shape2& sh) {
                            reinterpret_cast<pms_dev_counters*>(dm + b.off_ctr), sh, c.stream));
     if (timed) PMS_HIP(hipEventRecord(c.ev[2], c.stream));
     PMS_HIP(hipMemcpyAsync(c.h_back.as<char>(b.off_state), dm + b.off_state,
-                           b.meta_bytes - b.off_state, hipMemcpyDeviceToHost, c.stream));
+                           b.off_jobs - b.off_state, hipMemcpyDeviceToHost, c.stream));
     return PMS_OK;
 }
 
@@ -1256,10 +1261,9 @@ int pms_last_stats(pms_stats* out) {
         c.last.windows_ms = w_ms;
         c.last.kernel_ms = k_ms;
         if (c.dv_counters) {
-            pms_dev_state st;
-            pms_dev_counters ctr;
-            PMS_HIP(hipMemcpy(&st, c.dv_meta.as<char>(c.dv_state_off), sizeof(st), hipMemcpyDeviceToHost));
-            PMS_HIP(hipMemcpy(&ctr, c.dv_meta.as<char>(c.dv_ctr_off), sizeof(ctr), hipMemcpyDeviceToHost));
+            PMS_HIP(hipEventSynchronize(c.dv_back));
+            const pms_dev_state st = *c.hv_back.as<pms_dev_state>(c.dv_state_off);
+            const pms_dev_counters ctr = *c.hv_back.as<pms_dev_counters>(c.dv_ctr_off);
             c.last.seq_visits = st.visits;
             c.last.window_compares = st.visits * static_cast<uint64_t>(c.dv_nw);
             c.last.batches = ctr.batches;
@@ -1376,7 +1380,6 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     // every call; the window jobs and the work table only with a new plan.
     const bool whole = !reuse || c.dv_uploaded != c.dv_meta.p;
     memset(hm, 0, b.off_jobs);
-    memset(hm + b.off_state, 0, b.meta_bytes - b.off_state);
     pms_dev_instance* in = reinterpret_cast<pms_dev_instance*>(hm + b.off_insts);
     in->windows = c.dv_win.as<uint32_t>();
     in->out = dev_out;
@@ -1393,8 +1396,6 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
         PMS_HIP(hipMemcpyAsync(dm, hm, b.meta_bytes, hipMemcpyHostToDevice, s));
     } else {
         PMS_HIP(hipMemcpyAsync(dm, hm, b.off_jobs, hipMemcpyHostToDevice, s));
-        PMS_HIP(hipMemcpyAsync(dm + b.off_state, hm + b.off_state, b.meta_bytes - b.off_state,
-                               hipMemcpyHostToDevice, s));
     }
     PMS_HIP(hipEventRecord(c.dv_copied, s));
     c.dv_copy_live = true;
@@ -1414,6 +1415,11 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     PMS_HIP(hipEventRecord(c.ev[2], s));
     PMS_HIP(hipMemcpyAsync(dev_count, dm + b.off_state + offsetof(pms_dev_state, count),
                            sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    // The state and counters for pms_last_stats, without a synchronous copy.
+    PMS_TRY(c.hv_back.ensure(b.off_jobs));
+    PMS_HIP(hipMemcpyAsync(c.hv_back.as<char>(b.off_state), dm + b.off_state, b.off_jobs - b.off_state,
+                           hipMemcpyDeviceToHost, s));
+    PMS_HIP(hipEventRecord(c.dv_back, s));
     c.last = pms_stats{};
     c.last.grid = grid;
     c.last.wg_waves = waves;
