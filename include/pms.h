@@ -204,8 +204,10 @@ int pms_get_config(pms_config* cfg);
 int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_path,
                  pms_config* best);
 
-/* Counters of the last host-level solve on this device (or of the last
- * pms_solve_dev / pms_step_launch whose stream has been synchronised). */
+/* Counters of the last solve on this device.  After a device-level call
+ * (pms_solve_dev, pms_step_launch) pms_last_stats waits for that call's
+ * kernels and for its counters, which pms_solve_dev copies to pinned host
+ * memory on the caller's stream right after the search. */
 typedef struct {
     double kernel_ms;        /* search kernel, HIP events on its own stream */
     double windows_ms;       /* window-building kernel, HIP events */
