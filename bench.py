@@ -207,6 +207,17 @@ def bench_plain(args):
         opc, opc_src = None, "no counter run for this kernel"
     achieved = wc * opc / (k_ms * 1e-3) if opc else None
 
+    # The host-level call on the same instance (host rows in, sorted motifs
+    # out: validation, upload, both kernels, copy-back and sort).
+    host_walls, host_prep, host_finish = [], [], []
+    for _ in range(5):
+        h0 = time.perf_counter()
+        nat.solve(inst.seqs, l, d)
+        host_walls.append(time.perf_counter() - h0)
+        hs = nat.last_stats()
+        host_prep.append(hs["host_prep_ms"])
+        host_finish.append(hs["host_finish_ms"])
+
     parity = None
     gpath = os.path.join(ROOT, "tests", "golden", f"{args.config}.json")
     if os.path.exists(gpath):
@@ -249,6 +260,10 @@ def bench_plain(args):
         "motifs": int(codes.size),
         "parity_vs_golden": parity,
         "launch": {"grid": st["grid"], "wg_waves": st["wg_waves"], "chunk": st["chunk"]},
+        "host_level_pms_solve_ms": {"median": float(np.median(host_walls)) * 1e3,
+                                    "min": float(np.min(host_walls)) * 1e3,
+                                    "prep_median": float(np.median(host_prep)),
+                                    "finish_median": float(np.median(host_finish))},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12 if achieved else None,
