@@ -246,7 +246,9 @@ enum pms_probe_op {
     PMS_PROBE_ADD = 4,     /* v_add_u32 */
     PMS_PROBE_FMA_F32 = 5, /* v_fma_f32, for comparison with the published fp32 rate */
     PMS_PROBE_XOR_VV = 6,  /* v_xor_b32 with two VGPR sources */
-    PMS_PROBE_COMPARE = 7  /* the search loop's compare: xor, or_sdwa, bcnt, min3 (4 ops) */
+    PMS_PROBE_COMPARE = 7, /* the search loop's compare: xor, or_sdwa, bcnt, min3 (4 ops) */
+    PMS_PROBE_MOV_S = 8,   /* v_mov_b32 from an SGPR */
+    PMS_PROBE_MOV64_S = 9  /* v_mov_b64 from an SGPR pair (one op per 64-bit move) */
 };
 
 typedef struct {

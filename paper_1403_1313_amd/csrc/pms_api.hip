@@ -1488,7 +1488,7 @@ int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_p
 
 int pms_valu_probe(int op, int32_t waves_per_simd, int32_t iters_in, pms_probe_result* out) {
     g_last_error.clear();
-    if (!out || op < PMS_PROBE_XOR || op > PMS_PROBE_COMPARE)
+    if (!out || op < PMS_PROBE_XOR || op > PMS_PROBE_MOV64_S)
         return fail(PMS_ERR_INVALID, "bad probe op or NULL result");
     if (waves_per_simd < 0 || waves_per_simd > 16 || iters_in < 0 || iters_in > (1 << 24))
         return fail(PMS_ERR_INVALID, "probe size out of range");

@@ -23,7 +23,7 @@ SYMBOLS = ["pms_solve", "pms_solve_ex", "pms_solve_intersect", "pms_solve_many",
            "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev",
            "pms_valu_probe"]
 PROBE_OPS = {"xor": 0, "bcnt": 1, "min3": 2, "or_sdwa": 3, "add": 4, "fma_f32": 5, "xor_vv": 6,
-             "compare": 7}
+             "compare": 7, "mov_s": 8, "mov64_s": 9}
 
 
 class PmsError(RuntimeError):
