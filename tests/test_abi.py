@@ -252,3 +252,15 @@ def test_solve_intersect_rejects_large_balls():
     st, _, _ = nat.solve_intersect_raw(["ACGTNACGTACG"], 4, 1)
     assert st == nat.PMS_ERR_INVALID and "not A/C/G/T" in nat.last_error()
 
+
+
+def test_probe_rejects_unknown_kinds():
+    """pms_valu_probe checks the instruction kind before touching a device:
+    every enumerator of pms_probe_op is known to the binding, the values
+    around them are refused."""
+    text = open(HEADER).read()
+    kinds = {name: int(v) for name, v in re.findall(r"\b(PMS_PROBE_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    assert sorted(kinds.values()) == sorted(nat.PROBE_OPS.values())
+    r = nat.ProbeResult()
+    for bad in (-1, max(kinds.values()) + 1):
+        assert nat._lib.pms_valu_probe(bad, 0, 0, ctypes.byref(r)) == nat.PMS_ERR_INVALID
