@@ -90,9 +90,10 @@ int pms_solve_ex(const char* const* seqs, int32_t n, const int32_t* lengths, int
  * distance-d neighbourhoods (Hamming balls) of each sequence's windows, the
  * sample-driven form of the Planted Motif Search family that Section VI names
  * as future work.  The GPU keeps the candidate space as a 4^l-bit map
- * (2 x 2^(2l-3) bytes of device memory, 1 GiB at l = 16), sets the bits of
- * every window's neighbours with atomics, ANDs sequence by sequence, and
- * stops early when no candidate is left.  Work per sequence: (t-l+1) x
+ * (2^(2l-3) bytes of device memory, 512 MiB at l = 16); per sequence each
+ * workgroup sets the bits of every window's neighbours in one 2^18-bit tile
+ * of it in LDS and ANDs the tile into the map, and the passes stop early when
+ * no candidate is left.  Work per sequence: (t-l+1) x
  * |Ball| bit sets, |Ball| = sum_{k<=d} C(l,k) 3^k; far less than the sweep
  * when d is small against l, far more when it is not.  Arguments, output and
  * errors as for pms_solve; PMS_ERR_INVALID also when |Ball| exceeds

@@ -341,7 +341,7 @@ struct Ctx {
     bool bw_live[kJobRing] = {};
     int bw_next = 0;
     // neighbourhood-intersection method: bitmaps, window codes, ball masks
-    DevBuf nb_m, nb_b, nb_codes, nb_deltas, nb_cand, nb_out, nb_count;
+    DevBuf nb_m, nb_b, nb_codes, nb_deltas, nb_groups, nb_cand, nb_out, nb_count;
     int32_t nb_ball_l = -1, nb_ball_d = -1, nb_ball_size = 0;
 };
 
@@ -1083,13 +1083,27 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
     PMS_TRY(init_ctx(c));
     hipStream_t s = c.stream;
     const int32_t nw = t - l + 1;
-    const uint64_t bits = 1ull << (2 * l);
-    const uint64_t words = align_up(std::max<uint64_t>(1, bits / 32), 4);  // whole 16-byte vectors
+    // Tiles of 2^T candidate bits (at most 32 KiB of LDS), small enough that
+    // there are about 1024 of them from l = 9 on, the whole map below l = 4;
+    // the map is whole 16-byte vectors.
+    const int32_t T = 2 * l < 7 ? 2 * l : std::min(18, std::max(7, 2 * l - 10));
+    const uint32_t tiles = 1u << (2 * l - T);
+    const uint32_t tile_words = std::max<uint32_t>(4u, (1u << T) / 32u);
+    const uint64_t words = static_cast<uint64_t>(tiles) * tile_words;
     if (c.nb_ball_l != l || c.nb_ball_d != d) {
+        // The ball's masks grouped by their bits above T (group h: the masks
+        // that move a window's high bits by h), with the groups' offsets.
         std::vector<uint32_t> masks;
         ball_masks(l, d, masks);
+        std::stable_sort(masks.begin(), masks.end(),
+                         [T](uint32_t a, uint32_t b) { return (a >> T) < (b >> T); });
+        std::vector<uint32_t> off(tiles + 1, 0);
+        for (uint32_t x : masks) ++off[(x >> T) + 1];
+        for (uint32_t h = 0; h < tiles; ++h) off[h + 1] += off[h];
         PMS_TRY(c.nb_deltas.ensure(masks.size() * 4));
+        PMS_TRY(c.nb_groups.ensure(off.size() * 4));
         PMS_HIP(hipMemcpy(c.nb_deltas.p, masks.data(), masks.size() * 4, hipMemcpyHostToDevice));
+        PMS_HIP(hipMemcpy(c.nb_groups.p, off.data(), off.size() * 4, hipMemcpyHostToDevice));
         c.nb_ball_l = l;
         c.nb_ball_d = d;
         c.nb_ball_size = static_cast<int32_t>(masks.size());
@@ -1099,38 +1113,63 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
     PMS_TRY(c.h_raw.ensure(std::max<size_t>(static_cast<size_t>(n) * t, 256)));
     PMS_TRY(c.nb_codes.ensure(static_cast<size_t>(n) * nw * 4));
     PMS_TRY(c.nb_m.ensure(words * 4));
-    PMS_TRY(c.nb_b.ensure(words * 4));
     PMS_TRY(c.nb_count.ensure(256));
     PMS_TRY(c.h_back.ensure(256));
     for (int32_t r = 0; r < n; ++r) memcpy(c.h_raw.as<char>(static_cast<size_t>(r) * t), seqs[r], t);
     const double prep_ms = ms_since(t_call);
     uint32_t* m = c.nb_m.as<uint32_t>();
-    uint32_t* b = c.nb_b.as<uint32_t>();
     auto* cnt = c.nb_count.as<unsigned long long>();
     auto* h_cnt = c.h_back.as<unsigned long long>();
     const uint32_t grid = static_cast<uint32_t>(c.cus) * 16u;
     PMS_HIP(hipEventRecord(c.ev[0], s));
     PMS_HIP(hipMemcpyAsync(c.d_raw.p, c.h_raw.p, static_cast<size_t>(n) * t, hipMemcpyHostToDevice, s));
     PMS_HIP(pms::launch_nbhd_codes(c.d_raw.as<uint8_t>(), t, l, n, c.nb_codes.as<uint32_t>(), s));
-    // Bitmap passes while they are the cheaper way on: once the candidates
-    // left are few, checking them against the remaining sequences directly
-    // costs less than another pass (scatter plus three sweeps of the maps).
-    // Rates are round figures for one MI355X.
-    constexpr double kBitsPerS = 3e10, kStreamBytesPerS = 4e12, kComparesPerS = 5e12;
-    const double pass_s = static_cast<double>(nw) * nd / kBitsPerS +
-                          3.0 * static_cast<double>(words) * 4.0 / kStreamBytesPerS;
+    // Each pass is tiled or scattered, whichever costs less: a tiled pass
+    // pays for every tile's look-up of every window's mask group, the bits
+    // set in LDS and one or two streams of the map; a scatter pass pays for
+    // its global atomics, zeroing B and the AND (three streams after the
+    // first sequence).  Bitmap passes go on while they are the cheaper way:
+    // once the candidates left are few, checking them against the remaining
+    // sequences directly costs less than another pass.  Rates are round
+    // figures measured on one MI355X.
+    constexpr double kLdsBitsPerS = 1e12, kAtomicBitsPerS = 1e10, kStreamBytesPerS = 4e12,
+                     kLookupS = 6.4e-11, kComparesPerS = 5e12;
+    const double bits_set = static_cast<double>(nw) * nd;
+    const double map_bytes = static_cast<double>(words) * 4.0;
+    auto tiled_s = [&](bool first) {
+        return static_cast<double>(tiles) * nw * kLookupS + bits_set / kLdsBitsPerS +
+               (first ? 1.0 : 2.0) * map_bytes / kStreamBytesPerS;
+    };
+    auto scatter_s = [&](bool first) {
+        return bits_set / kAtomicBitsPerS + (first ? 1.0 : 4.0) * map_bytes / kStreamBytesPerS;
+    };
+    bool tiled_first = tiled_s(true) <= scatter_s(true);
+    bool tiled_next = tiled_s(false) <= scatter_s(false);
+    // PMS_TEST_NBHD_PASS=tiled|scatter forces one form (tests of both).
+    if (const char* v = getenv("PMS_TEST_NBHD_PASS")) {
+        if (!strcmp(v, "tiled")) tiled_first = tiled_next = true;
+        if (!strcmp(v, "scatter")) tiled_first = tiled_next = false;
+    }
+    const double pass_s = std::min(tiled_s(false), scatter_s(false));
+    if (!tiled_next && n > 1) PMS_TRY(c.nb_b.ensure(words * 4));
     uint64_t left = 0, visits = 0;
     int32_t scanned = 0;
     bool verified = false;
     for (int32_t i = 0; i < n; ++i) {
-        uint32_t* target = i == 0 ? m : b;
-        PMS_HIP(pms::launch_nbhd_zero(target, words, grid, s));
         PMS_HIP(pms::launch_fill(reinterpret_cast<uint32_t*>(cnt), 8, 0u, s));
-        // The first sequence's map is M; its scatter counts the bits it sets.
-        PMS_HIP(pms::launch_nbhd_scatter(c.nb_codes.as<uint32_t>() + static_cast<size_t>(i) * nw, nw,
-                                         c.nb_deltas.as<uint32_t>(), nd, target,
-                                         i == 0 ? cnt : nullptr, grid, s));
-        if (i > 0) PMS_HIP(pms::launch_nbhd_and(m, b, words, cnt, grid, s));  // M &= B
+        // M = B for the first sequence, M &= B after; cnt counts M's bits.
+        const uint32_t* codes_i = c.nb_codes.as<uint32_t>() + static_cast<size_t>(i) * nw;
+        if (i == 0 ? tiled_first : tiled_next) {
+            PMS_HIP(pms::launch_nbhd_tile(codes_i, nw, c.nb_deltas.as<uint32_t>(),
+                                          c.nb_groups.as<uint32_t>(), T, tiles, tile_words, m,
+                                          i == 0, cnt, s));
+        } else {
+            uint32_t* target = i == 0 ? m : c.nb_b.as<uint32_t>();
+            PMS_HIP(pms::launch_nbhd_zero(target, words, grid, s));
+            PMS_HIP(pms::launch_nbhd_scatter(codes_i, nw, c.nb_deltas.as<uint32_t>(), nd, target,
+                                             i == 0 ? cnt : nullptr, grid, s));
+            if (i > 0) PMS_HIP(pms::launch_nbhd_and(m, target, words, cnt, grid, s));
+        }
         PMS_HIP(hipMemcpyAsync(h_cnt, cnt, 8, hipMemcpyDeviceToHost, s));
         PMS_HIP(hipStreamSynchronize(s));
         left = h_cnt[0];

@@ -50,6 +50,14 @@ hipError_t launch_nbhd_scatter(const uint32_t* codes, int32_t nw, const uint32_t
                                uint32_t grid, hipStream_t stream);
 hipError_t launch_nbhd_and(uint32_t* m, const uint32_t* b, uint64_t words,
                            unsigned long long* count, uint32_t grid, hipStream_t stream);
+// One pass
+// over a sequence: `tiles` workgroups of 2^T candidate bits (tile_words words
+// each); group_off has tiles + 1 entries (masks sorted by their bits above T).
+size_t nbhd_tile_lds_bytes(uint32_t tile_words);
+hipError_t launch_nbhd_tile(const uint32_t* codes, int32_t nw, const uint32_t* deltas,
+                            const uint32_t* group_off, int32_t T, uint32_t tiles,
+                            uint32_t tile_words, uint32_t* m, bool first,
+                            unsigned long long* count, hipStream_t stream);
 hipError_t launch_nbhd_collect(const uint32_t* m, uint64_t words, uint32_t* out, uint64_t cap,
                                unsigned long long* count, uint32_t grid, hipStream_t stream);
 hipError_t launch_nbhd_verify(const uint32_t* cand, uint64_t count, const uint32_t* codes,

@@ -11,17 +11,20 @@
 // bits in device memory:
 //
 //   pms_nbhd_codes_kernel    window codes of every row (one thread a window)
-//   pms_nbhd_scatter_kernel  sets bit (w ^ delta) of a row's bitmap for every
-//                            window w and mask delta (global atomicOr)
-//   pms_nbhd_and_kernel      M &= B over the bitmaps, counting the bits left
+//   pms_nbhd_tile_kernel     one sequence's pass: bit (w ^ delta) of B for every
+//                            window w and mask delta, tile by tile in LDS, and
+//                            M = B or M &= B for each tile, counting the bits
+//   pms_nbhd_zero_kernel,    the same pass for few bits: zero B, set its bits
+//   pms_nbhd_scatter_kernel, with global atomics (counting the fresh ones on
+//   pms_nbhd_and_kernel      the first sequence), then M &= B
 //   pms_nbhd_collect_kernel  motif codes of the set bits of M (one global
 //                            atomicAdd per wavefront)
 //   pms_nbhd_verify_kernel   once few candidates are left, checks them against
 //                            the remaining sequences directly
 //
-// Bound: the scatter issues nw x |Ball| atomics per sequence into a bitmap
-// that stays in the on-chip caches for l <= 15; zeroing, AND and collection
-// stream the bitmaps in 16-byte vectors.
+// Bound: a tiled pass sets nw x |Ball| bits with LDS atomics and streams M
+// once in and once out (16-byte vectors); a scatter pass issues nw x |Ball|
+// global atomics and streams the maps three times; collection streams M once.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -52,6 +55,12 @@ pms_nbhd_codes_kernel(const uint8_t* __restrict__ seqs, int32_t t, int32_t l, in
 
 // Bitmaps are handled as whole 16-byte vectors: their length in words is a
 // multiple of 4 (the words past 4^l bits stay zero).
+
+// A bitmap pass takes one of two forms, whichever the host's cost model
+// finds cheaper for the sequence: the tiled pass (every bit set in LDS, the
+// map streamed once or twice) when there are many bits per tile, or the
+// scatter pass (zero B, set its bits with global atomics, M &= B) when there
+// are few.
 
 // Zeroes `vecs` 16-byte vectors.
 extern "C" __global__ void __launch_bounds__(256)
@@ -99,6 +108,130 @@ pms_nbhd_and_kernel(uint4* __restrict__ m, const uint4* __restrict__ b, uint64_t
         const uint4 x = m[k], y = b[k];
         const uint4 v = make_uint4(x.x & y.x, x.y & y.y, x.z & y.z, x.w & y.w);
         m[k] = v;
+        bits += static_cast<uint32_t>(__builtin_popcount(v.x) + __builtin_popcount(v.y) +
+                                      __builtin_popcount(v.z) + __builtin_popcount(v.w));
+    }
+    unsigned long long v = bits;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane_id() == 0 && v) atomicAdd(count, v);
+}
+
+// One bitmap pass by tiles: workgroup g builds in LDS the bits
+// [g 2^T, (g+1) 2^T) of B, the union of the sequence's window balls, then
+// writes that tile of M as B (first sequence) or M & B, counting the bits it
+// keeps (one atomic per wavefront).  Every bit is set with an LDS atomic; HBM
+// sees one read and one write of M per pass.
+//
+// The ball's masks are sorted by their bits above T, group h holding
+// deltas[group_off[h] .. group_off[h+1]), so the masks that take window w into
+// tile g are group (w >> T) ^ g, at most 2^T of them.  Windows are taken
+// kTileChunk at a time; an LDS prefix sum numbers their (window, mask) pairs
+// (at most kTileChunk x 2^T < 2^32) and each thread takes an equal run of
+// them.  LDS: tile_words + 3 kTileChunk + 1 + kTileThreads words.
+constexpr int kTileChunk = 1024;
+#ifndef PMS_TILE_THREADS
+#define PMS_TILE_THREADS 256
+#endif
+constexpr int kTileThreads = PMS_TILE_THREADS;
+constexpr int kScanPer = kTileChunk / kTileThreads;   // prefix entries per thread
+constexpr int kPartPer = kTileThreads / 64;           // thread sums per lane of the scan
+
+extern "C" __global__ void __launch_bounds__(kTileThreads)
+pms_nbhd_tile_kernel(const uint32_t* __restrict__ codes, int32_t nw,
+                     const uint32_t* __restrict__ deltas, const uint32_t* __restrict__ group_off,
+                     int32_t T, uint32_t tile_words, uint4* __restrict__ m, int32_t first,
+                     unsigned long long* __restrict__ count) {
+    extern __shared__ uint32_t lds[];
+    uint32_t* const tile = lds;
+    uint32_t* const pre = tile + tile_words;         // kTileChunk + 1: pairs before window j
+    uint32_t* const beg = pre + kTileChunk + 1;      // kTileChunk: first mask of window j's group
+    uint32_t* const win = beg + kTileChunk;          // kTileChunk: window codes
+    uint32_t* const part = win + kTileChunk;         // kTileThreads: per-thread sums of the scan
+    const uint32_t g = blockIdx.x;
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t low = (1u << T) - 1u;
+    for (uint32_t k = tid; k < tile_words; k += nt) tile[k] = 0u;
+    for (int32_t c0 = 0; c0 < nw; c0 += kTileChunk) {
+        const uint32_t cn = static_cast<uint32_t>(min(kTileChunk, nw - c0));
+        __syncthreads();  // the tile is clear and the last chunk's pairs are done
+        for (uint32_t j = tid; j < cn; j += nt) {
+            const uint32_t w = codes[c0 + j];
+            const uint32_t h = (w >> T) ^ g;
+            const uint32_t lo = group_off[h];
+            win[j] = w;
+            beg[j] = lo;
+            pre[j + 1] = group_off[h + 1] - lo;
+        }
+        __syncthreads();
+        // Inclusive scan of pre[1 .. cn]: thread t sums its kScanPer entries,
+        // the first wavefront scans the thread sums (kPartPer per lane), and
+        // each thread adds its offset to its entries.
+        const uint32_t e0 = kScanPer * tid + 1;
+        uint32_t run = 0;
+        for (uint32_t j = e0; j < e0 + kScanPer && j <= cn; ++j) run += pre[j];
+        part[tid] = run;
+        __syncthreads();
+        if (tid < 64) {
+            uint32_t v[kPartPer], sum = 0;
+#pragma unroll
+            for (int u = 0; u < kPartPer; ++u) {
+                v[u] = part[kPartPer * tid + u];
+                sum += v[u];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (static_cast<int>(tid) >= off) incl += y;
+            }
+            uint32_t base = incl - sum;
+#pragma unroll
+            for (int u = 0; u < kPartPer; ++u) {
+                part[kPartPer * tid + u] = base;
+                base += v[u];
+            }
+        }
+        __syncthreads();
+        {
+            uint32_t acc = part[tid];
+            for (uint32_t j = e0; j < e0 + kScanPer && j <= cn; ++j) {
+                acc += pre[j];
+                pre[j] = acc;
+            }
+        }
+        if (tid == 0) pre[0] = 0u;
+        __syncthreads();
+        const uint32_t total = pre[cn];
+        const uint32_t p0 = static_cast<uint32_t>(static_cast<uint64_t>(total) * tid / nt);
+        const uint32_t p1 = static_cast<uint32_t>(static_cast<uint64_t>(total) * (tid + 1) / nt);
+        if (p0 < p1) {
+            // The window of pair p0: the last j with pre[j] <= p0.
+            uint32_t lo = 0, hi = cn;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (pre[mid] <= p0) lo = mid; else hi = mid;
+            }
+            uint32_t j = lo;
+            for (uint32_t q = p0; q < p1; ++q) {
+                while (pre[j + 1] <= q) ++j;
+                const uint32_t x = (win[j] ^ deltas[beg[j] + (q - pre[j])]) & low;
+                atomicOr(tile + (x >> 5), 1u << (x & 31u));
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t vecs = tile_words / 4;
+    uint4* const out = m + static_cast<uint64_t>(g) * vecs;
+    const uint4* const tv = reinterpret_cast<const uint4*>(tile);
+    uint32_t bits = 0;
+    for (uint32_t k = tid; k < vecs; k += nt) {
+        uint4 v = tv[k];
+        if (!first) {
+            const uint4 o = out[k];
+            v = make_uint4(v.x & o.x, v.y & o.y, v.z & o.z, v.w & o.w);
+        }
+        out[k] = v;
         bits += static_cast<uint32_t>(__builtin_popcount(v.x) + __builtin_popcount(v.y) +
                                       __builtin_popcount(v.z) + __builtin_popcount(v.w));
     }
@@ -261,6 +394,20 @@ hipError_t launch_nbhd_and(uint32_t* m, const uint32_t* b, uint64_t words,
     hipLaunchKernelGGL(pms_nbhd_and_kernel, dim3(grid), dim3(256), 0, stream,
                        reinterpret_cast<uint4*>(m), reinterpret_cast<const uint4*>(b), words / 4,
                        count);
+    return hipGetLastError();
+}
+
+size_t nbhd_tile_lds_bytes(uint32_t tile_words) {
+    return (static_cast<size_t>(tile_words) + 3 * kTileChunk + 1 + kTileThreads) * sizeof(uint32_t);
+}
+
+hipError_t launch_nbhd_tile(const uint32_t* codes, int32_t nw, const uint32_t* deltas,
+                            const uint32_t* group_off, int32_t T, uint32_t tiles,
+                            uint32_t tile_words, uint32_t* m, bool first,
+                            unsigned long long* count, hipStream_t stream) {
+    hipLaunchKernelGGL(pms_nbhd_tile_kernel, dim3(tiles), dim3(kTileThreads),
+                       nbhd_tile_lds_bytes(tile_words), stream, codes, nw, deltas, group_off, T,
+                       tile_words, reinterpret_cast<uint4*>(m), first ? 1 : 0, count);
     return hipGetLastError();
 }
 

@@ -84,3 +84,24 @@ def test_intersect_capacity_and_stats(nat):
     s = nat.last_stats()
     ball = sum(__import__("math").comb(7, k) * 3 ** k for k in range(4))
     assert s["window_compares"] == s["batches"] * (60 - 7 + 1) * ball
+
+
+@pytest.mark.parametrize("form", ["tiled", "scatter"])
+def test_intersect_each_pass_form(nat, monkeypatch, form):
+    """Both forms of a bitmap pass, forced: random small cases (one tile at
+    l <= 3, several from l = 4) and planted ones up to l = 16, exact."""
+    monkeypatch.setenv("PMS_TEST_NBHD_PASS", form)
+    rng = np.random.default_rng(311)
+    for case in range(16):
+        l = int(rng.integers(1, 10))
+        d = int(rng.integers(0, min(l, 3) + 1))
+        n = int(rng.integers(1, 7))
+        t = int(rng.integers(l, 1500 if case % 4 == 0 else 120))
+        seqs = fmgen.random_seqs(n, t, 7000 + case)
+        announce(f"intersect {form} l={l} d={d} n={n} t={t}")
+        want = oracle.solve(seqs, l, d, mode="skip", cap=4 ** l)
+        assert np.array_equal(nat.solve_intersect(seqs, l, d), want), (l, d, n, t)
+    for (l, d, n, t, seed) in [(13, 3, 8, 400, 21), (16, 2, 6, 300, 22)]:
+        inst = fmgen.gen_fm(l, d, n, t, seed)
+        announce(f"intersect {form} planted ({l},{d})")
+        assert np.array_equal(nat.solve_intersect(inst.seqs, l, d), nat.solve(inst.seqs, l, d))
