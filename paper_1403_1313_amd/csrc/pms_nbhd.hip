@@ -127,8 +127,8 @@ pms_nbhd_and_kernel(uint4* __restrict__ m, const uint4* __restrict__ b, uint64_t
 // deltas[group_off[h] .. group_off[h+1]), so the masks that take window w into
 // tile g are group (w >> T) ^ g, at most 2^T of them.  Windows are taken
 // kTileChunk at a time; an LDS prefix sum numbers their (window, mask) pairs
-// (at most kTileChunk x 2^T < 2^32) and each thread takes an equal run of
-// them.  LDS: tile_words + 3 kTileChunk + 1 + kTileThreads words.
+// (at most kTileChunk x 2^T < 2^32) and each thread takes an equal run.
+// LDS: tile_words + 3 kTileChunk + 1 + kTileThreads words.
 constexpr int kTileChunk = 1024;
 #ifndef PMS_TILE_THREADS
 #define PMS_TILE_THREADS 256
@@ -136,6 +136,7 @@ constexpr int kTileChunk = 1024;
 constexpr int kTileThreads = PMS_TILE_THREADS;
 constexpr int kScanPer = kTileChunk / kTileThreads;   // prefix entries per thread
 constexpr int kPartPer = kTileThreads / 64;           // thread sums per lane of the scan
+constexpr int kPairUnroll = 4;                        // mask loads in flight per lane
 
 extern "C" __global__ void __launch_bounds__(kTileThreads)
 pms_nbhd_tile_kernel(const uint32_t* __restrict__ codes, int32_t nw,
@@ -206,17 +207,34 @@ pms_nbhd_tile_kernel(const uint32_t* __restrict__ codes, int32_t nw,
         const uint32_t p0 = static_cast<uint32_t>(static_cast<uint64_t>(total) * tid / nt);
         const uint32_t p1 = static_cast<uint32_t>(static_cast<uint64_t>(total) * (tid + 1) / nt);
         if (p0 < p1) {
-            // The window of pair p0: the last j with pre[j] <= p0.
+            // Each thread takes one run of pairs, so the lanes of a
+            // wavefront work on different windows and their LDS atomics
+            // rarely meet in one word; kPairUnroll mask loads are in flight.
+            // j(q), the last j with pre[j] <= q, only grows along the run.
             uint32_t lo = 0, hi = cn;
             while (hi - lo > 1) {
                 const uint32_t mid = (lo + hi) >> 1;
                 if (pre[mid] <= p0) lo = mid; else hi = mid;
             }
             uint32_t j = lo;
-            for (uint32_t q = p0; q < p1; ++q) {
-                while (pre[j + 1] <= q) ++j;
-                const uint32_t x = (win[j] ^ deltas[beg[j] + (q - pre[j])]) & low;
-                atomicOr(tile + (x >> 5), 1u << (x & 31u));
+            for (uint32_t q0 = p0; q0 < p1; q0 += kPairUnroll) {
+                uint32_t wv[kPairUnroll], dv[kPairUnroll];
+#pragma unroll
+                for (int u = 0; u < kPairUnroll; ++u) {
+                    const uint32_t q = q0 + u;
+                    if (q < p1) {
+                        while (pre[j + 1] <= q) ++j;
+                        wv[u] = win[j];
+                        dv[u] = deltas[beg[j] + (q - pre[j])];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kPairUnroll; ++u) {
+                    if (q0 + u < p1) {
+                        const uint32_t x = (wv[u] ^ dv[u]) & low;
+                        atomicOr(tile + (x >> 5), 1u << (x & 31u));
+                    }
+                }
             }
         }
     }
