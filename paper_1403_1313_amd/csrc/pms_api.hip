@@ -1152,6 +1152,10 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
     }
     const double pass_s = std::min(tiled_s(false), scatter_s(false));
     if (!tiled_next && n > 1) PMS_TRY(c.nb_b.ensure(words * 4));
+    // PMS_TEST_NBHD_VERIFY_AFTER=<k> checks the survivors directly after k
+    // passes whatever the cost model says (tests of both verify kernels).
+    int32_t verify_after = 0;
+    if (const char* v = getenv("PMS_TEST_NBHD_VERIFY_AFTER")) verify_after = atoi(v);
     uint64_t left = 0, visits = 0;
     int32_t scanned = 0;
     bool verified = false;
@@ -1176,7 +1180,8 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
         ++scanned;
         if (left == 0 || i + 1 == n) break;
         const double verify_s = static_cast<double>(left) * nw * 1.1 / kComparesPerS;
-        if (verify_s > pass_s) continue;
+        const bool forced = verify_after > 0 && scanned >= verify_after;
+        if (!forced && verify_s > pass_s) continue;
         // The candidates left, then sequences i+1 .. n-1 checked directly.
         PMS_TRY(c.nb_cand.ensure(left * 4));
         PMS_TRY(c.nb_out.ensure(left * 4));

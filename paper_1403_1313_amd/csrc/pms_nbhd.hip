@@ -19,8 +19,10 @@
 //   pms_nbhd_and_kernel      the first sequence), then M &= B
 //   pms_nbhd_collect_kernel  motif codes of the set bits of M (one global
 //                            atomicAdd per wavefront)
-//   pms_nbhd_verify_kernel   once few candidates are left, checks them against
-//                            the remaining sequences directly
+//   pms_nbhd_verify_kernel,  once few candidates are left, checks them against
+//   pms_nbhd_verify_lds_     the remaining sequences directly (the rows' codes
+//   kernel, ..._lds4_kernel  staged in LDS when they fit; one or four lanes
+//                            per survivor)
 //
 // Bound: a tiled pass sets nw x |Ball| bits with LDS atomics and streams M
 // once in and once out (16-byte vectors); a scatter pass issues nw x |Ball|
@@ -28,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "pms.h"
 #include "pms_device.h"
@@ -316,7 +320,14 @@ pms_nbhd_collect_kernel(const uint4* __restrict__ m, uint64_t vecs, uint32_t* __
 // directly: lane k takes survivor k; the wavefront scans one sequence at a
 // time (window codes wave-uniform), a lane whose smallest distance exceeds d
 // drops out, and the wavefront stops at the first sequence no lane passes
-// (the enhanced rule of Section III.A).  Distance of codes x, w: the 2-bit
+// (the enhanced rule of Section III.A).  A wavefront with a lane that keeps
+// passing scans every remaining sequence, so the kernel's time is that
+// chain's: when the remaining rows' codes fit in kVerifyLdsBytes of LDS each
+// workgroup stages them once (rows padded to a multiple of 4 windows with
+// window 0, which cannot change a minimum) and the scan reads 4 codes per
+// LDS load, 16 in flight, with four lanes per survivor (each a quarter of
+// the windows) while survivors are few; otherwise the codes come through
+// the scalar data cache, 16 per load.  Distance of codes x, w: the 2-bit
 // digits that differ, popcount(((x ^ w) | (x ^ w) >> 1) & 0x55555555).
 // Passing codes are appended to `out` (at most `cap`), *out_count counts
 // them all; *visits counts (survivor, sequence) scans.
@@ -371,14 +382,130 @@ pms_nbhd_verify_kernel(const uint32_t* __restrict__ cand, uint64_t count,
     if (lane_id() == 0 && seen) atomicAdd(visits, seen);
 }
 
+constexpr size_t kVerifyLdsBytes = 48 * 1024;
+constexpr uint64_t kVerifyQuadMax = 3u << 16;   // survivors checked four lanes each
+
+template <int kLanes>
+__device__ __forceinline__ void verify_lds(const uint32_t* __restrict__ cand, uint64_t count,
+                           const uint32_t* __restrict__ codes, int32_t nw, int32_t nw_pad,
+                           int32_t s_begin, int32_t n, int32_t d, uint32_t* __restrict__ out,
+                           uint64_t cap, unsigned long long* __restrict__ out_count,
+                           unsigned long long* __restrict__ visits) {
+    extern __shared__ uint4 rows4[];
+    uint32_t* const rows = reinterpret_cast<uint32_t*>(rows4);
+    const int32_t nrows = n - s_begin;
+    for (int32_t k = threadIdx.x; k < nrows * nw_pad; k += blockDim.x) {
+        const int32_t r = k / nw_pad, j = k - r * nw_pad;
+        rows[k] = codes[static_cast<int64_t>(s_begin + r) * nw + (j < nw ? j : 0)];
+    }
+    __syncthreads();
+    // kLanes lanes per survivor (1 or 4), each taking every kLanes-th group
+    // of 4 windows, so one survivor's scan is 1/kLanes as long; the minima
+    // meet by shuffles.  A wavefront holds 64 / kLanes survivors.
+    const int32_t nq = nw_pad / 4;
+    const uint32_t lane = lane_id(), part = lane & static_cast<uint32_t>(kLanes - 1);
+    const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x / kLanes;
+    const uint64_t first = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u)) / kLanes;
+    // lane kLanes * i speaks for survivor i
+    constexpr uint64_t kLeaders = kLanes == 4 ? 0x1111111111111111ull : ~0ull;
+    unsigned long long seen = 0;
+    for (uint64_t k0 = first; k0 < count; k0 += step) {
+        const uint64_t k = k0 + lane / kLanes;
+        bool alive = k < count;
+        const uint32_t x = alive ? cand[k] : 0u;
+        for (int32_t s = s_begin; s < n; ++s) {
+            const uint64_t live = ballot(alive);
+            if (!live) break;
+            seen += static_cast<unsigned long long>(__builtin_popcountll(live & kLeaders));
+            const uint4* w4 = rows4 + static_cast<int64_t>(s - s_begin) * nq;
+            uint32_t best = 32u;
+            int32_t q = static_cast<int32_t>(part);
+            for (; q + 3 * kLanes < nq; q += 4 * kLanes) {
+                uint4 c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) c[u] = w4[q + kLanes * u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    best = min(best, digit_mismatches(x, c[u].x));
+                    best = min(best, digit_mismatches(x, c[u].y));
+                    best = min(best, digit_mismatches(x, c[u].z));
+                    best = min(best, digit_mismatches(x, c[u].w));
+                }
+            }
+            for (; q < nq; q += kLanes) {
+                const uint4 c = w4[q];
+                best = min(best, digit_mismatches(x, c.x));
+                best = min(best, digit_mismatches(x, c.y));
+                best = min(best, digit_mismatches(x, c.z));
+                best = min(best, digit_mismatches(x, c.w));
+            }
+            if constexpr (kLanes == 4) {
+                best = min(best, static_cast<uint32_t>(__shfl_xor(static_cast<int>(best), 1, 64)));
+                best = min(best, static_cast<uint32_t>(__shfl_xor(static_cast<int>(best), 2, 64)));
+            }
+            alive = alive && best <= static_cast<uint32_t>(d);
+        }
+        const bool lead = alive && part == 0u;
+        const uint64_t pass = ballot(lead);
+        if (pass) {
+            unsigned long long base = 0;
+            if (lane == 0)
+                base = atomicAdd(out_count, static_cast<unsigned long long>(__builtin_popcountll(pass)));
+            base = uni64(base);
+            if (lead) {
+                const uint64_t at = base + rank_below(pass);
+                if (at < cap) out[at] = x;
+            }
+        }
+    }
+    if (lane == 0 && seen) atomicAdd(visits, seen);
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+pms_nbhd_verify_lds_kernel(const uint32_t* __restrict__ cand, uint64_t count,
+                           const uint32_t* __restrict__ codes, int32_t nw, int32_t nw_pad,
+                           int32_t s_begin, int32_t n, int32_t d, uint32_t* __restrict__ out,
+                           uint64_t cap, unsigned long long* __restrict__ out_count,
+                           unsigned long long* __restrict__ visits) {
+    verify_lds<1>(cand, count, codes, nw, nw_pad, s_begin, n, d, out, cap, out_count, visits);
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+pms_nbhd_verify_lds4_kernel(const uint32_t* __restrict__ cand, uint64_t count,
+                            const uint32_t* __restrict__ codes, int32_t nw, int32_t nw_pad,
+                            int32_t s_begin, int32_t n, int32_t d, uint32_t* __restrict__ out,
+                            uint64_t cap, unsigned long long* __restrict__ out_count,
+                            unsigned long long* __restrict__ visits) {
+    verify_lds<4>(cand, count, codes, nw, nw_pad, s_begin, n, d, out, cap, out_count, visits);
+}
+
 namespace pms {
 
 hipError_t launch_nbhd_verify(const uint32_t* cand, uint64_t count, const uint32_t* codes,
                               int32_t nw, int32_t s_begin, int32_t n, int32_t d, uint32_t* out,
                               uint64_t cap, unsigned long long* out_count,
                               unsigned long long* visits, uint32_t grid, hipStream_t stream) {
-    hipLaunchKernelGGL(pms_nbhd_verify_kernel, dim3(grid), dim3(256), 0, stream, cand, count,
-                       codes, nw, s_begin, n, d, out, cap, out_count, visits);
+    // No more workgroups than survivors need (one lane each): idle ones
+    // would only be launched and retired (and, below, stage rows for nothing).
+    const uint64_t need_lds = (count * 4 + 255) / 256;   // four lanes per survivor
+    const uint64_t need = (count + 255) / 256;
+    const uint32_t blocks = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(grid, need)));
+    const int32_t nw_pad = (nw + 3) & ~3;
+    const size_t lds = static_cast<size_t>(n - s_begin) * nw_pad * sizeof(uint32_t);
+    // Four lanes per survivor while survivors are few enough that a lane
+    // each would leave the device idle; beyond that every workgroup would
+    // stage the rows for a quarter as many survivors.
+    if (n > s_begin && lds <= kVerifyLdsBytes && count <= kVerifyQuadMax)
+        hipLaunchKernelGGL(pms_nbhd_verify_lds4_kernel,
+                           dim3(static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(grid, need_lds)))),
+                           dim3(256), lds, stream, cand,
+                           count, codes, nw, nw_pad, s_begin, n, d, out, cap, out_count, visits);
+    else if (n > s_begin && lds <= kVerifyLdsBytes)
+        hipLaunchKernelGGL(pms_nbhd_verify_lds_kernel, dim3(blocks), dim3(256), lds, stream, cand,
+                           count, codes, nw, nw_pad, s_begin, n, d, out, cap, out_count, visits);
+    else
+        hipLaunchKernelGGL(pms_nbhd_verify_kernel, dim3(blocks), dim3(256), 0, stream, cand, count,
+                           codes, nw, s_begin, n, d, out, cap, out_count, visits);
     return hipGetLastError();
 }
 

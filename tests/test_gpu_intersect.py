@@ -105,3 +105,18 @@ def test_intersect_each_pass_form(nat, monkeypatch, form):
         inst = fmgen.gen_fm(l, d, n, t, seed)
         announce(f"intersect {form} planted ({l},{d})")
         assert np.array_equal(nat.solve_intersect(inst.seqs, l, d), nat.solve(inst.seqs, l, d))
+
+
+@pytest.mark.parametrize("t", [200, 9000])
+def test_intersect_verify_kernels(nat, monkeypatch, t):
+    """Survivors checked directly after one pass: rows staged in LDS (t =
+    200) or read through the scalar cache (t = 9000: two rows of codes are
+    more than the LDS staging takes), against the oracle."""
+    monkeypatch.setenv("PMS_TEST_NBHD_VERIFY_AFTER", "1")
+    for (l, d, n, seed) in [(8, 1, 3, 1), (8, 2, 3, 2), (6, 1, 5, 3)]:
+        seqs = fmgen.random_seqs(n, t, 8000 + seed)
+        announce(f"intersect verify l={l} d={d} n={n} t={t}")
+        want = oracle.solve(seqs, l, d, mode="skip", cap=4 ** l)
+        got = nat.solve_intersect(seqs, l, d)
+        assert np.array_equal(got, want), (l, d, n, t)
+        assert nat.last_stats()["batches"] == 1
