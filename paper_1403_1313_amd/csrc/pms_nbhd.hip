@@ -18,7 +18,7 @@
 //   pms_nbhd_scatter_kernel, with global atomics (counting the fresh ones on
 //   pms_nbhd_and_kernel      the first sequence), then M &= B
 //   pms_nbhd_collect_kernel  motif codes of the set bits of M (one global
-//                            atomicAdd per wavefront)
+//                            atomicAdd per workgroup)
 //   pms_nbhd_verify_kernel,  once few candidates are left, checks them against
 //   pms_nbhd_verify_lds_     the remaining sequences directly (the rows' codes
 //   kernel, ..._lds4_kernel  staged in LDS when they fit; one or four lanes
@@ -264,48 +264,88 @@ pms_nbhd_tile_kernel(const uint32_t* __restrict__ codes, int32_t nw,
 }
 
 // Codes of the set bits of M (`vecs` 16-byte vectors), unsorted, at most
-// `cap` written; *count receives the number of set bits.  Each lane has
-// kCollectBatch vectors in flight per round (a sparse map is almost all
-// zeros, so the loop is otherwise bound by load latency).  A round that
-// finds bits reserves room for all of them with one atomic per wavefront
-// and an inclusive scan of the lanes' counts, so the shared counter sees a
-// single atomic per round however many bits there are.
+// `cap` written; *count receives the number of set bits.  Workgroup g takes
+// one contiguous share of M and reads it twice: first it counts the share's
+// bits and reserves room for all of them with a single atomic, then it
+// writes them, each batch of kCollectBatch vectors per thread placed by a
+// workgroup-wide scan of the threads' counts.  One atomic per workgroup
+// (a counter shared by every wavefront of the grid serialised the earlier
+// one-atomic-per-round form when the bits were many and sparse).
 constexpr int kCollectBatch = 8;
+
+__device__ __forceinline__ uint32_t popc4(const uint4& v) {
+    return static_cast<uint32_t>(__builtin_popcount(v.x) + __builtin_popcount(v.y) +
+                                 __builtin_popcount(v.z) + __builtin_popcount(v.w));
+}
 
 extern "C" __global__ void __launch_bounds__(256)
 pms_nbhd_collect_kernel(const uint4* __restrict__ m, uint64_t vecs, uint32_t* __restrict__ out,
                         uint64_t cap, unsigned long long* __restrict__ count) {
-    const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    const uint32_t lane = lane_id();
-    // Whole wavefronts iterate together so the ballots and shuffles see every lane.
-    const uint64_t first = static_cast<uint64_t>(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
-    for (uint64_t k0 = first; k0 < vecs; k0 += step * kCollectBatch) {
+    __shared__ uint32_t wtot[4];
+    __shared__ unsigned long long base_s;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    constexpr uint32_t kSpan = 256u * kCollectBatch;
+    const uint64_t per = (vecs + gridDim.x - 1) / gridDim.x;
+    const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * per;
+    const uint64_t hi = lo + per < vecs ? lo + per : vecs;
+    // Count the share's bits, kCollectBatch loads in flight per thread.
+    uint32_t bits = 0;
+    for (uint64_t k0 = lo; k0 < hi; k0 += kSpan) {
         uint4 x[kCollectBatch];
 #pragma unroll
         for (int u = 0; u < kCollectBatch; ++u) {
-            const uint64_t k = k0 + u * step + lane;
-            x[u] = k < vecs ? m[k] : make_uint4(0u, 0u, 0u, 0u);
+            const uint64_t k = k0 + u * 256u + tid;
+            x[u] = k < hi ? m[k] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < kCollectBatch; ++u) bits += popc4(x[u]);
+    }
+    uint32_t wsum = bits;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+    if (lane == 0) wtot[wave] = wsum;
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned long long total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+        base_s = total ? atomicAdd(count, total) : 0ull;
+        wtot[0] = static_cast<uint32_t>(total != 0);
+    }
+    __syncthreads();
+    if (!wtot[0]) return;
+    uint64_t run = base_s;
+    __syncthreads();
+    // Write them: per batch, thread t's bits go after those of threads < t.
+    for (uint64_t k0 = lo; k0 < hi; k0 += kSpan) {
+        uint4 x[kCollectBatch];
+#pragma unroll
+        for (int u = 0; u < kCollectBatch; ++u) {
+            const uint64_t k = k0 + u * 256u + tid;
+            x[u] = k < hi ? m[k] : make_uint4(0u, 0u, 0u, 0u);
         }
         uint32_t mine = 0;
 #pragma unroll
-        for (int u = 0; u < kCollectBatch; ++u)
-            mine += static_cast<uint32_t>(__builtin_popcount(x[u].x) + __builtin_popcount(x[u].y) +
-                                          __builtin_popcount(x[u].z) + __builtin_popcount(x[u].w));
-        if (!ballot(mine != 0u)) continue;
-        uint32_t incl = mine;  // inclusive scan of the lanes' counts
+        for (int u = 0; u < kCollectBatch; ++u) mine += popc4(x[u]);
+        uint32_t incl = mine;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t v = __shfl_up(incl, off, 64);
             if (lane >= static_cast<uint32_t>(off)) incl += v;
         }
-        const uint32_t total = __shfl(incl, 63, 64);
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(count, static_cast<unsigned long long>(total));
-        base = uni64(base);
-        uint64_t at = base + (incl - mine);
+        if (lane == 63) wtot[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < 4; ++w) {
+            const uint32_t t = wtot[w];
+            before += w < wave ? t : 0u;
+            total += t;
+        }
+        __syncthreads();   // wtot is rewritten by the next batch
+        if (!total) continue;
+        uint64_t at = run + before + (incl - mine);
 #pragma unroll
         for (int u = 0; u < kCollectBatch; ++u) {
-            const uint64_t k = k0 + u * step + lane;
+            const uint64_t k = k0 + u * 256u + tid;
             const uint32_t w4[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -313,6 +353,7 @@ pms_nbhd_collect_kernel(const uint4* __restrict__ m, uint64_t vecs, uint32_t* __
                     if (at < cap) out[at] = static_cast<uint32_t>((4 * k + e) * 32 + __builtin_ctz(v));
             }
         }
+        run += total;
     }
 }
 
