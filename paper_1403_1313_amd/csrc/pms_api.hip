@@ -341,8 +341,9 @@ struct Ctx {
     bool bw_live[kJobRing] = {};
     int bw_next = 0;
     // neighbourhood-intersection method: bitmaps, window codes, ball masks
-    DevBuf nb_m, nb_b, nb_codes, nb_deltas, nb_groups, nb_cand, nb_out, nb_count;
-    int32_t nb_ball_l = -1, nb_ball_d = -1, nb_ball_size = 0;
+    DevBuf nb_m, nb_b, nb_codes, nb_deltas, nb_groups, nb_ne, nb_cand, nb_out, nb_count;
+    DevBuf nb_tcount, nb_toff, nb_tcur, nb_rec, nb_part;
+    int32_t nb_ball_l = -1, nb_ball_d = -1, nb_ball_size = 0, nb_nne = 0;
 };
 
 Ctx g_ctx;
@@ -1100,13 +1101,19 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
         std::vector<uint32_t> off(tiles + 1, 0);
         for (uint32_t x : masks) ++off[(x >> T) + 1];
         for (uint32_t h = 0; h < tiles; ++h) off[h + 1] += off[h];
+        std::vector<uint32_t> ne;   // the non-empty groups
+        for (uint32_t h = 0; h < tiles; ++h)
+            if (off[h + 1] > off[h]) ne.push_back(h);
         PMS_TRY(c.nb_deltas.ensure(masks.size() * 4));
         PMS_TRY(c.nb_groups.ensure(off.size() * 4));
+        PMS_TRY(c.nb_ne.ensure(ne.size() * 4));
         PMS_HIP(hipMemcpy(c.nb_deltas.p, masks.data(), masks.size() * 4, hipMemcpyHostToDevice));
         PMS_HIP(hipMemcpy(c.nb_groups.p, off.data(), off.size() * 4, hipMemcpyHostToDevice));
+        PMS_HIP(hipMemcpy(c.nb_ne.p, ne.data(), ne.size() * 4, hipMemcpyHostToDevice));
         c.nb_ball_l = l;
         c.nb_ball_d = d;
         c.nb_ball_size = static_cast<int32_t>(masks.size());
+        c.nb_nne = static_cast<int32_t>(ne.size());
     }
     const int32_t nd = c.nb_ball_size;
     PMS_TRY(c.d_raw.ensure(std::max<size_t>(static_cast<size_t>(n) * t, 256)));
@@ -1132,12 +1139,21 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
     // once the candidates left are few, checking them against the remaining
     // sequences directly costs less than another pass.  Rates are round
     // figures measured on one MI355X.
-    constexpr double kLdsBitsPerS = 1e12, kAtomicBitsPerS = 1e10, kStreamBytesPerS = 4e12,
-                     kLookupS = 6.4e-11, kComparesPerS = 5e12;
+    // A tiled pass finds each tile's (window, group) pairs either by looking
+    // up every window's group in every tile or, when that is dearer, from
+    // records sorted by tile (count, scan, fill: nw x non-empty groups).
+    constexpr double kLdsBitsPerS = 3e11, kAtomicBitsPerS = 1e10, kStreamBytesPerS = 4e12,
+                     kLookupS = 7.6e-12, kRecordS = 4e-11, kRecordFixedS = 2e-5,
+                     kComparesPerS = 5e12;
+    constexpr uint64_t kMaxRecords = 1u << 24;
     const double bits_set = static_cast<double>(nw) * nd;
     const double map_bytes = static_cast<double>(words) * 4.0;
+    const uint64_t records = static_cast<uint64_t>(nw) * static_cast<uint64_t>(c.nb_nne);
+    const double lookup_s = static_cast<double>(tiles) * nw * kLookupS;
+    const double record_s = static_cast<double>(records) * kRecordS + kRecordFixedS;
+    bool use_records = records <= kMaxRecords && record_s < lookup_s;
     auto tiled_s = [&](bool first) {
-        return static_cast<double>(tiles) * nw * kLookupS + bits_set / kLdsBitsPerS +
+        return (use_records ? record_s : lookup_s) + bits_set / kLdsBitsPerS +
                (first ? 1.0 : 2.0) * map_bytes / kStreamBytesPerS;
     };
     auto scatter_s = [&](bool first) {
@@ -1145,10 +1161,21 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
     };
     bool tiled_first = tiled_s(true) <= scatter_s(true);
     bool tiled_next = tiled_s(false) <= scatter_s(false);
-    // PMS_TEST_NBHD_PASS=tiled|scatter forces one form (tests of both).
+    // PMS_TEST_NBHD_PASS=tiled|records|scatter forces one form (tests of
+    // every form): tiled with look-ups, tiled with records, or scattered.
     if (const char* v = getenv("PMS_TEST_NBHD_PASS")) {
-        if (!strcmp(v, "tiled")) tiled_first = tiled_next = true;
+        if (!strcmp(v, "tiled")) tiled_first = tiled_next = true, use_records = false;
+        if (!strcmp(v, "records") && records <= kMaxRecords)
+            tiled_first = tiled_next = true, use_records = true;
         if (!strcmp(v, "scatter")) tiled_first = tiled_next = false;
+    }
+    PMS_TRY(c.nb_part.ensure(static_cast<size_t>(std::max<uint32_t>(tiles, grid)) * 4));
+    uint32_t* const part = c.nb_part.as<uint32_t>();
+    if ((tiled_first || tiled_next) && use_records) {
+        PMS_TRY(c.nb_tcount.ensure(static_cast<size_t>(tiles) * 4));
+        PMS_TRY(c.nb_toff.ensure(static_cast<size_t>(tiles + 1) * 4));
+        PMS_TRY(c.nb_tcur.ensure(static_cast<size_t>(tiles) * 4));
+        PMS_TRY(c.nb_rec.ensure(std::max<uint64_t>(records, 1) * 4));
     }
     const double pass_s = std::min(tiled_s(false), scatter_s(false));
     if (!tiled_next && n > 1) PMS_TRY(c.nb_b.ensure(words * 4));
@@ -1164,15 +1191,27 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
         // M = B for the first sequence, M &= B after; cnt counts M's bits.
         const uint32_t* codes_i = c.nb_codes.as<uint32_t>() + static_cast<size_t>(i) * nw;
         if (i == 0 ? tiled_first : tiled_next) {
+            const uint32_t* rec = nullptr;
+            const uint32_t* rec_off = nullptr;
+            if (use_records) {
+                PMS_HIP(pms::launch_nbhd_records(codes_i, nw, c.nb_ne.as<uint32_t>(), c.nb_nne, T, tiles,
+                                                 c.nb_tcount.as<uint32_t>(), c.nb_toff.as<uint32_t>(),
+                                                 c.nb_tcur.as<uint32_t>(), c.nb_rec.as<uint32_t>(), grid,
+                                                 s));
+                rec = c.nb_rec.as<uint32_t>();
+                rec_off = c.nb_toff.as<uint32_t>();
+            }
             PMS_HIP(pms::launch_nbhd_tile(codes_i, nw, c.nb_deltas.as<uint32_t>(),
-                                          c.nb_groups.as<uint32_t>(), T, tiles, tile_words, m,
-                                          i == 0, cnt, s));
+                                          c.nb_groups.as<uint32_t>(), rec, rec_off, T, tiles,
+                                          tile_words, m, i == 0, part, s));
+            PMS_HIP(pms::launch_nbhd_sum(part, tiles, cnt, s));
         } else {
             uint32_t* target = i == 0 ? m : c.nb_b.as<uint32_t>();
             PMS_HIP(pms::launch_nbhd_zero(target, words, grid, s));
             PMS_HIP(pms::launch_nbhd_scatter(codes_i, nw, c.nb_deltas.as<uint32_t>(), nd, target,
-                                             i == 0 ? cnt : nullptr, grid, s));
-            if (i > 0) PMS_HIP(pms::launch_nbhd_and(m, target, words, cnt, grid, s));
+                                             i == 0 ? part : nullptr, grid, s));
+            if (i > 0) PMS_HIP(pms::launch_nbhd_and(m, target, words, part, grid, s));
+            PMS_HIP(pms::launch_nbhd_sum(part, grid, cnt, s));
         }
         PMS_HIP(hipMemcpyAsync(h_cnt, cnt, 8, hipMemcpyDeviceToHost, s));
         PMS_HIP(hipStreamSynchronize(s));

@@ -45,19 +45,31 @@ hipError_t launch_nbhd_codes(const uint8_t* seqs, int32_t t, int32_t l, int32_t 
                              uint32_t* codes, hipStream_t stream);
 // Bitmap lengths in words are multiples of 4 (16-byte vectors).
 hipError_t launch_nbhd_zero(uint32_t* p, uint64_t words, uint32_t grid, hipStream_t stream);
+// Pass counts come per workgroup (part[blockIdx]) and are summed by
+// launch_nbhd_sum into one uint64.
 hipError_t launch_nbhd_scatter(const uint32_t* codes, int32_t nw, const uint32_t* deltas,
-                               int32_t nd, uint32_t* bitmap, unsigned long long* fresh,
+                               int32_t nd, uint32_t* bitmap, uint32_t* fresh,
                                uint32_t grid, hipStream_t stream);
 hipError_t launch_nbhd_and(uint32_t* m, const uint32_t* b, uint64_t words,
-                           unsigned long long* count, uint32_t grid, hipStream_t stream);
+                           uint32_t* part, uint32_t grid, hipStream_t stream);
+hipError_t launch_nbhd_sum(const uint32_t* part, uint32_t n, unsigned long long* total,
+                           hipStream_t stream);
 // One pass
 // over a sequence: `tiles` workgroups of 2^T candidate bits (tile_words words
 // each); group_off has tiles + 1 entries (masks sorted by their bits above T).
 size_t nbhd_tile_lds_bytes(uint32_t tile_words);
+// rec/rec_off (may be null): the tile's (window, group) records, as built by
+// launch_nbhd_records; without them every tile looks up every window.
 hipError_t launch_nbhd_tile(const uint32_t* codes, int32_t nw, const uint32_t* deltas,
-                            const uint32_t* group_off, int32_t T, uint32_t tiles,
+                            const uint32_t* group_off, const uint32_t* rec,
+                            const uint32_t* rec_off, int32_t T, uint32_t tiles,
                             uint32_t tile_words, uint32_t* m, bool first,
-                            unsigned long long* count, hipStream_t stream);
+                            uint32_t* part, hipStream_t stream);
+// Records of one pass: ne[0 .. nne) the non-empty mask groups; tcount and
+// tcur hold tiles words, toff tiles + 1, rec nw x nne.
+hipError_t launch_nbhd_records(const uint32_t* codes, int32_t nw, const uint32_t* ne, int32_t nne,
+                               int32_t T, uint32_t tiles, uint32_t* tcount, uint32_t* toff,
+                               uint32_t* tcur, uint32_t* rec, uint32_t grid, hipStream_t stream);
 hipError_t launch_nbhd_collect(const uint32_t* m, uint64_t words, uint32_t* out, uint64_t cap,
                                unsigned long long* count, uint32_t grid, hipStream_t stream);
 hipError_t launch_nbhd_verify(const uint32_t* cand, uint64_t count, const uint32_t* codes,

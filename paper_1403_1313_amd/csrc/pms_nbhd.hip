@@ -11,6 +11,7 @@
 // bits in device memory:
 //
 //   pms_nbhd_codes_kernel    window codes of every row (one thread a window)
+//   pms_nbhd_rec_*_kernel    (window, mask group) records by destination tile
 //   pms_nbhd_tile_kernel     one sequence's pass: bit (w ^ delta) of B for every
 //                            window w and mask delta, tile by tile in LDS, and
 //                            M = B or M &= B for each tile, counting the bits
@@ -66,6 +67,36 @@ pms_nbhd_codes_kernel(const uint8_t* __restrict__ seqs, int32_t t, int32_t l, in
 // scatter pass (zero B, set its bits with global atomics, M &= B) when there
 // are few.
 
+// Counts of a pass are summed per workgroup (four wavefronts) into
+// part[blockIdx.x] and then by pms_nbhd_sum_kernel: an atomic per wavefront
+// on one counter serialises when there are tens of thousands of them.
+__device__ __forceinline__ void block_count(uint32_t v, uint32_t* __restrict__ part) {
+    __shared__ uint32_t wsum[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane_id() == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// *total = part[0] + ... + part[n-1] (one workgroup of 1024 threads).
+extern "C" __global__ void __launch_bounds__(1024)
+pms_nbhd_sum_kernel(const uint32_t* __restrict__ part, uint32_t n,
+                    unsigned long long* __restrict__ total) {
+    __shared__ unsigned long long wsum[16];
+    unsigned long long v = 0;
+    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) v += part[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane_id() == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 16; ++w) t += wsum[w];
+        *total = t;
+    }
+}
+
 // Zeroes `vecs` 16-byte vectors.
 extern "C" __global__ void __launch_bounds__(256)
 pms_nbhd_zero_kernel(uint4* __restrict__ p, uint64_t vecs) {
@@ -76,12 +107,12 @@ pms_nbhd_zero_kernel(uint4* __restrict__ p, uint64_t vecs) {
 
 // Every (window, mask) pair of one row: a grid-stride loop over the pairs,
 // mask index fastest, so a wavefront reads consecutive masks and one window.
-// `fresh` (optional) counts the bits this pass set that were clear, from the
-// values the atomics return (one atomicAdd per wavefront).
+// `fresh` (optional) receives per workgroup the bits this pass set that
+// were clear, from the values the atomics return.
 extern "C" __global__ void __launch_bounds__(256)
 pms_nbhd_scatter_kernel(const uint32_t* __restrict__ codes, int32_t nw,
                         const uint32_t* __restrict__ deltas, int32_t nd,
-                        uint32_t* __restrict__ bitmap, unsigned long long* __restrict__ fresh) {
+                        uint32_t* __restrict__ bitmap, uint32_t* __restrict__ fresh) {
     const int64_t pairs = static_cast<int64_t>(nw) * nd;
     const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
     uint32_t set = 0;
@@ -92,19 +123,14 @@ pms_nbhd_scatter_kernel(const uint32_t* __restrict__ codes, int32_t nw,
         const uint32_t bit = 1u << (x & 31u);
         set += (atomicOr(bitmap + (x >> 5), bit) & bit) ? 0u : 1u;
     }
-    if (fresh) {
-        unsigned long long v = set;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane_id() == 0 && v) atomicAdd(fresh, v);
-    }
+    if (fresh) block_count(set, fresh);
 }
 
-// M &= B over `vecs` 16-byte vectors; `count` accumulates the bits left (one
-// atomic per wavefront).
+// M &= B over `vecs` 16-byte vectors; `part` receives per workgroup the
+// bits left.
 extern "C" __global__ void __launch_bounds__(256)
 pms_nbhd_and_kernel(uint4* __restrict__ m, const uint4* __restrict__ b, uint64_t vecs,
-                    unsigned long long* __restrict__ count) {
+                    uint32_t* __restrict__ part) {
     const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     uint32_t bits = 0;
     for (uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < vecs;
@@ -115,16 +141,84 @@ pms_nbhd_and_kernel(uint4* __restrict__ m, const uint4* __restrict__ b, uint64_t
         bits += static_cast<uint32_t>(__builtin_popcount(v.x) + __builtin_popcount(v.y) +
                                       __builtin_popcount(v.z) + __builtin_popcount(v.w));
     }
-    unsigned long long v = bits;
+    block_count(bits, part);
+}
+
+// A record: window index in the low 17 bits (t <= 2^17), mask group above.
+constexpr uint32_t kRecGroupShift = 17;
+constexpr uint32_t kRecWindowMask = (1u << kRecGroupShift) - 1u;
+
+// Records of a tiled pass: every (window j, non-empty mask group h) pair
+// belongs to tile (w_j >> T) ^ h.  With records a tile reads its own pairs
+// instead of looking up every window's group, which pays when there are
+// many more tiles than groups per window (l = 16: 16384 tiles, 585 windows,
+// about a thousand non-empty groups).  Count per tile, exclusive scan, fill.
+extern "C" __global__ void __launch_bounds__(256)
+pms_nbhd_rec_count_kernel(const uint32_t* __restrict__ codes, int32_t nw,
+                          const uint32_t* __restrict__ ne, int32_t nne, int32_t T,
+                          uint32_t* __restrict__ tcount) {
+    const uint64_t total = static_cast<uint64_t>(nw) * static_cast<uint64_t>(nne);
+    const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += step) {
+        const uint32_t j = static_cast<uint32_t>(i / static_cast<uint64_t>(nne));
+        const uint32_t k = static_cast<uint32_t>(i - static_cast<uint64_t>(j) * nne);
+        atomicAdd(tcount + ((codes[j] >> T) ^ ne[k]), 1u);
+    }
+}
+
+// Exclusive scan of tiles (<= 16384) counts into toff[0 .. tiles], one
+// workgroup of 1024 threads; tcur (tiles words) is cleared for the fill.
+extern "C" __global__ void __launch_bounds__(1024)
+pms_nbhd_rec_scan_kernel(const uint32_t* __restrict__ tcount, uint32_t tiles,
+                         uint32_t* __restrict__ toff, uint32_t* __restrict__ tcur) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t per = (tiles + 1023u) / 1024u;
+    const uint32_t e0 = tid * per;
+    uint32_t mine = 0;
+    for (uint32_t e = e0; e < e0 + per && e < tiles; ++e) mine += tcount[e];
+    uint32_t incl = mine;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane_id() == 0 && v) atomicAdd(count, v);
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        if (lane >= static_cast<uint32_t>(off)) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+        before += w < wave ? wsum[w] : 0u;
+        total += wsum[w];
+    }
+    uint32_t run = before + incl - mine;
+    for (uint32_t e = e0; e < e0 + per && e < tiles; ++e) {
+        toff[e] = run;
+        run += tcount[e];
+        tcur[e] = 0u;
+    }
+    if (tid == 0) toff[tiles] = total;
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+pms_nbhd_rec_fill_kernel(const uint32_t* __restrict__ codes, int32_t nw,
+                         const uint32_t* __restrict__ ne, int32_t nne, int32_t T,
+                         const uint32_t* __restrict__ toff, uint32_t* __restrict__ tcur,
+                         uint32_t* __restrict__ rec) {
+    const uint64_t total = static_cast<uint64_t>(nw) * static_cast<uint64_t>(nne);
+    const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += step) {
+        const uint32_t j = static_cast<uint32_t>(i / static_cast<uint64_t>(nne));
+        const uint32_t k = static_cast<uint32_t>(i - static_cast<uint64_t>(j) * nne);
+        const uint32_t h = ne[k];
+        const uint32_t tile = (codes[j] >> T) ^ h;
+        rec[toff[tile] + atomicAdd(tcur + tile, 1u)] = j | (h << kRecGroupShift);
+    }
 }
 
 // One bitmap pass by tiles: workgroup g builds in LDS the bits
 // [g 2^T, (g+1) 2^T) of B, the union of the sequence's window balls, then
 // writes that tile of M as B (first sequence) or M & B, counting the bits it
-// keeps (one atomic per wavefront).  Every bit is set with an LDS atomic; HBM
+// keeps into tile_bits[g].  Every bit is set with an LDS atomic; HBM
 // sees one read and one write of M per pass.
 //
 // The ball's masks are sorted by their bits above T, group h holding
@@ -145,8 +239,9 @@ constexpr int kPairUnroll = 4;                        // mask loads in flight pe
 extern "C" __global__ void __launch_bounds__(kTileThreads)
 pms_nbhd_tile_kernel(const uint32_t* __restrict__ codes, int32_t nw,
                      const uint32_t* __restrict__ deltas, const uint32_t* __restrict__ group_off,
+                     const uint32_t* __restrict__ rec, const uint32_t* __restrict__ rec_off,
                      int32_t T, uint32_t tile_words, uint4* __restrict__ m, int32_t first,
-                     unsigned long long* __restrict__ count) {
+                     uint32_t* __restrict__ tile_bits) {
     extern __shared__ uint32_t lds[];
     uint32_t* const tile = lds;
     uint32_t* const pre = tile + tile_words;         // kTileChunk + 1: pairs before window j
@@ -156,13 +251,24 @@ pms_nbhd_tile_kernel(const uint32_t* __restrict__ codes, int32_t nw,
     const uint32_t g = blockIdx.x;
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
     const uint32_t low = (1u << T) - 1u;
+    // Items: the tile's records (window, group) when given, else every
+    // window with its group (w >> T) ^ g.
+    const uint32_t ibase = rec ? rec_off[g] : 0u;
+    const int32_t nitems = rec ? static_cast<int32_t>(rec_off[g + 1] - ibase) : nw;
     for (uint32_t k = tid; k < tile_words; k += nt) tile[k] = 0u;
-    for (int32_t c0 = 0; c0 < nw; c0 += kTileChunk) {
-        const uint32_t cn = static_cast<uint32_t>(min(kTileChunk, nw - c0));
+    for (int32_t c0 = 0; c0 < nitems; c0 += kTileChunk) {
+        const uint32_t cn = static_cast<uint32_t>(min(kTileChunk, nitems - c0));
         __syncthreads();  // the tile is clear and the last chunk's pairs are done
         for (uint32_t j = tid; j < cn; j += nt) {
-            const uint32_t w = codes[c0 + j];
-            const uint32_t h = (w >> T) ^ g;
+            uint32_t w, h;
+            if (rec) {
+                const uint32_t r = rec[ibase + c0 + j];
+                w = codes[r & kRecWindowMask];
+                h = r >> kRecGroupShift;
+            } else {
+                w = codes[c0 + j];
+                h = (w >> T) ^ g;
+            }
             const uint32_t lo = group_off[h];
             win[j] = w;
             beg[j] = lo;
@@ -214,7 +320,9 @@ pms_nbhd_tile_kernel(const uint32_t* __restrict__ codes, int32_t nw,
             // Each thread takes one run of pairs, so the lanes of a
             // wavefront work on different windows and their LDS atomics
             // rarely meet in one word; kPairUnroll mask loads are in flight.
-            // j(q), the last j with pre[j] <= q, only grows along the run.
+            // j(q), the last j with pre[j] <= q, only grows along the run
+            // (walking window by window instead, each lane with its own
+            // segment lengths, diverged and was slower).
             uint32_t lo = 0, hi = cn;
             while (hi - lo > 1) {
                 const uint32_t mid = (lo + hi) >> 1;
@@ -257,10 +365,7 @@ pms_nbhd_tile_kernel(const uint32_t* __restrict__ codes, int32_t nw,
         bits += static_cast<uint32_t>(__builtin_popcount(v.x) + __builtin_popcount(v.y) +
                                       __builtin_popcount(v.z) + __builtin_popcount(v.w));
     }
-    unsigned long long v = bits;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane_id() == 0 && v) atomicAdd(count, v);
+    block_count(bits, tile_bits);
 }
 
 // Codes of the set bits of M (`vecs` 16-byte vectors), unsorted, at most
@@ -568,7 +673,7 @@ hipError_t launch_nbhd_zero(uint32_t* p, uint64_t words, uint32_t grid, hipStrea
 }
 
 hipError_t launch_nbhd_scatter(const uint32_t* codes, int32_t nw, const uint32_t* deltas,
-                               int32_t nd, uint32_t* bitmap, unsigned long long* fresh,
+                               int32_t nd, uint32_t* bitmap, uint32_t* fresh,
                                uint32_t grid, hipStream_t stream) {
     hipLaunchKernelGGL(pms_nbhd_scatter_kernel, dim3(grid), dim3(256), 0, stream, codes, nw,
                        deltas, nd, bitmap, fresh);
@@ -576,10 +681,16 @@ hipError_t launch_nbhd_scatter(const uint32_t* codes, int32_t nw, const uint32_t
 }
 
 hipError_t launch_nbhd_and(uint32_t* m, const uint32_t* b, uint64_t words,
-                           unsigned long long* count, uint32_t grid, hipStream_t stream) {
+                           uint32_t* part, uint32_t grid, hipStream_t stream) {
     hipLaunchKernelGGL(pms_nbhd_and_kernel, dim3(grid), dim3(256), 0, stream,
                        reinterpret_cast<uint4*>(m), reinterpret_cast<const uint4*>(b), words / 4,
-                       count);
+                       part);
+    return hipGetLastError();
+}
+
+hipError_t launch_nbhd_sum(const uint32_t* part, uint32_t n, unsigned long long* total,
+                           hipStream_t stream) {
+    hipLaunchKernelGGL(pms_nbhd_sum_kernel, dim3(1), dim3(1024), 0, stream, part, n, total);
     return hipGetLastError();
 }
 
@@ -588,12 +699,27 @@ size_t nbhd_tile_lds_bytes(uint32_t tile_words) {
 }
 
 hipError_t launch_nbhd_tile(const uint32_t* codes, int32_t nw, const uint32_t* deltas,
-                            const uint32_t* group_off, int32_t T, uint32_t tiles,
+                            const uint32_t* group_off, const uint32_t* rec,
+                            const uint32_t* rec_off, int32_t T, uint32_t tiles,
                             uint32_t tile_words, uint32_t* m, bool first,
-                            unsigned long long* count, hipStream_t stream) {
+                            uint32_t* part, hipStream_t stream) {
     hipLaunchKernelGGL(pms_nbhd_tile_kernel, dim3(tiles), dim3(kTileThreads),
-                       nbhd_tile_lds_bytes(tile_words), stream, codes, nw, deltas, group_off, T,
-                       tile_words, reinterpret_cast<uint4*>(m), first ? 1 : 0, count);
+                       nbhd_tile_lds_bytes(tile_words), stream, codes, nw, deltas, group_off, rec,
+                       rec_off, T, tile_words, reinterpret_cast<uint4*>(m), first ? 1 : 0, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_nbhd_records(const uint32_t* codes, int32_t nw, const uint32_t* ne, int32_t nne,
+                               int32_t T, uint32_t tiles, uint32_t* tcount, uint32_t* toff,
+                               uint32_t* tcur, uint32_t* rec, uint32_t grid, hipStream_t stream) {
+    hipError_t e = launch_fill(tcount, tiles, 0u, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pms_nbhd_rec_count_kernel, dim3(grid), dim3(256), 0, stream, codes, nw, ne,
+                       nne, T, tcount);
+    hipLaunchKernelGGL(pms_nbhd_rec_scan_kernel, dim3(1), dim3(1024), 0, stream, tcount, tiles, toff,
+                       tcur);
+    hipLaunchKernelGGL(pms_nbhd_rec_fill_kernel, dim3(grid), dim3(256), 0, stream, codes, nw, ne,
+                       nne, T, toff, tcur, rec);
     return hipGetLastError();
 }
 

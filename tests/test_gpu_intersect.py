@@ -86,9 +86,9 @@ def test_intersect_capacity_and_stats(nat):
     assert s["window_compares"] == s["batches"] * (60 - 7 + 1) * ball
 
 
-@pytest.mark.parametrize("form", ["tiled", "scatter"])
+@pytest.mark.parametrize("form", ["tiled", "records", "scatter"])
 def test_intersect_each_pass_form(nat, monkeypatch, form):
-    """Both forms of a bitmap pass, forced: random small cases (one tile at
+    """Every form of a bitmap pass, forced: random small cases (one tile at
     l <= 3, several from l = 4) and planted ones up to l = 16, exact."""
     monkeypatch.setenv("PMS_TEST_NBHD_PASS", form)
     rng = np.random.default_rng(311)
