@@ -116,7 +116,7 @@ pms_config default_config() {
     c.chunk = 1u << 14;
     c.wg_waves = 4;
     c.wgs_per_cu = 0;
-    c.tail_split = 8;
+    c.tail_split = 0;
     c.variant = PMS_VARIANT_AUTO;
     return c;
 }
@@ -1542,24 +1542,27 @@ int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_p
     double best_ms = 1e300;
     const uint32_t chunks[] = {1u << 11, 1u << 12, 1u << 13, 1u << 14, 1u << 15, 1u << 16};
     const uint32_t waves[] = {1, 2, 4, 8};
+    const uint32_t tails[] = {0, 8};
     for (uint32_t ch : chunks) {
         if (ch > total && ch != chunks[0]) continue;
         for (uint32_t w : waves) {
-            pms_config cfg{ch, w, 0, 8, c.cfg.variant};
-            Batch b;
-            b.shape = {Shape{n, t, l, d}};
-            b.rows = {ptrs.data()};
-            b.out_cap = {0};
-            plan_batch(b, cfg, target_items(c));
-            PMS_TRY(stage_batch(c, b));
-            double ms = 1e300;
-            for (int rep = 0; rep < 3; ++rep) {
-                PMS_TRY(run_batch(c, b, cfg, false));
-                ms = std::min(ms, c.last.kernel_ms);
-            }
-            if (ms < best_ms) {
-                best_ms = ms;
-                best_cfg = cfg;
+            for (uint32_t tail : tails) {
+                pms_config cfg{ch, w, 0, tail, c.cfg.variant};
+                Batch b;
+                b.shape = {Shape{n, t, l, d}};
+                b.rows = {ptrs.data()};
+                b.out_cap = {0};
+                plan_batch(b, cfg, target_items(c));
+                PMS_TRY(stage_batch(c, b));
+                double ms = 1e300;
+                for (int rep = 0; rep < 3; ++rep) {
+                    PMS_TRY(run_batch(c, b, cfg, false));
+                    ms = std::min(ms, c.last.kernel_ms);
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_cfg = cfg;
+                }
             }
         }
     }

@@ -335,7 +335,7 @@ def decode(code: int, l: int) -> str:
     return buf.raw[:l].decode()
 
 
-def set_config(chunk=0, wg_waves=0, wgs_per_cu=0, tail_split=8, variant=0, reset=False):
+def set_config(chunk=0, wg_waves=0, wgs_per_cu=0, tail_split=0, variant=0, reset=False):
     if reset:
         return _check(_lib.pms_set_config(None))
     cfg = Config(chunk, wg_waves, wgs_per_cu, tail_split, variant)
