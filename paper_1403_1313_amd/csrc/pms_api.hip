@@ -462,11 +462,15 @@ void build_work(Batch& b, const std::vector<int>& order, const std::vector<doubl
         const uint64_t total = 1ull << (2 * s.l);
         const double share = total_cost > 0 ? cost[i] / total_cost : 1.0;
         const uint64_t want_items = std::max<uint64_t>(1, static_cast<uint64_t>(share * target_items));
+        // Items start on multiples of 4096 candidates where the space allows
+        // (64 groups of 64: the grouped kernel's stage-0 batches then share
+        // all but three prefix bases).
+        const uint64_t unit = total >= 4096 ? 4096 : 64;
         uint64_t size = std::max<uint64_t>(cfg.chunk, (total + want_items - 1) / want_items);
-        size = std::min<uint64_t>(align_up(size, 64), 1ull << 30);
-        const uint64_t tail = total * cfg.tail_split / 64;
-        const uint64_t head_end = total - tail;
-        const uint64_t small = std::max<uint64_t>(64, align_up(size / 4, 64));
+        size = std::min<uint64_t>(align_up(size, unit), 1ull << 30);
+        const uint64_t tail = align_up(total * cfg.tail_split / 64, unit);
+        const uint64_t head_end = total - std::min(tail, total);
+        const uint64_t small = std::max<uint64_t>(unit, align_up(size / 4, unit));
         uint64_t k = 0;
         while (k < total) {
             const uint64_t step = k < head_end ? size : small;

@@ -302,6 +302,138 @@ __device__ __forceinline__ typename MaskOf<S>::type scan_group_any(
     }
 }
 
+// Stage-0 scan of 64 consecutive groups that start on a multiple of 64: the
+// lanes then share their first Q = P - 3 prefix bases (`shared`, the group
+// number over 64) and differ only in the last three, which are the base-4
+// digits of the lane index.
+//  * Once per call, lane j counts the shared positions' mismatches for
+//    window group j (carry-save, bias 19 - d, c' = c + 19 - d < 32) and keeps
+//    the thresholds U_k = [c <= d - k], k = 0..6, as comparisons of c' with
+//    the constants 19 - k.
+//  * Per 32 windows every lane fetches U_0..U_6 of the current window group
+//    from lane gi (ds_bpermute) and walks them through its own three prefix
+//    positions with the selection recursion of the suffix:
+//      V_1[k] = m_1 ? U[k+1] : U[k]    (k = 0..5)
+//      V_2[k] = m_2 ? V_1[k+1] : V_1[k] (k = 0..4)
+//      T[k]   = m_3 ? V_2[k+1] : V_2[k] (k = 0..3)
+//    so T[k] = [mismatches over the whole prefix <= d - k], as in scan_group.
+// The prefix count over Q positions is thus done once per call instead of
+// once per window group per lane, and no prefix word of the shared positions
+// is read per iteration.  Requires 3 <= P <= 13 and groups <= 64.
+template <int P>
+__device__ __forceinline__ uint64_t scan_group_s0(cu32* W, uint32_t groups, uint32_t shared,
+                                                  uint32_t lane, int d, uint64_t alive) {
+    constexpr int S = 3;
+    constexpr int L = P + S;
+    constexpr int Q = P - 3;           // shared prefix positions
+    constexpr int K = 64;
+    constexpr int N1 = K / 4;
+    // Lane-derived values (the row offset below, the lane's prefix masks)
+    // are rebuilt per call: hoisted out of the persistent loop, they would
+    // hold registers through every other path as well.
+    uint32_t ln = lane;
+    asm volatile("" : "+v"(ln));
+    uint32_t u[7];
+    {
+        const uint32_t bias_value = static_cast<uint32_t>(19 - d);
+        uint32_t bias[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) bias[i] = 0u - ((bias_value >> i) & 1u);
+        uint32_t m[Q > 0 ? Q : 1];
+#pragma unroll
+        for (int p = 0; p < (Q > 0 ? Q : 1); ++p) m[p] = 0u;
+        if (ln < groups) {
+            const uint32_t* row = (const uint32_t*)(W) + ln * (2u * L);
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const uint32_t b = (shared >> (2 * (Q - 1 - p))) & 3u;
+                m[p] = (row[p] ^ (0u - (b >> 1))) | (row[L + p] ^ (0u - (b & 1u)));
+            }
+        }
+        uint32_t c[5];
+        count_bits<Q>(m, bias, c);
+        u[0] = ~(c[4] & (c[3] | c[2]));
+        u[1] = ~(c[4] & (c[3] | c[2] | (c[1] & c[0])));
+        u[2] = ~(c[4] & (c[3] | c[2] | c[1]));
+        u[3] = ~(c[4] & (c[3] | c[2] | c[1] | c[0]));
+        u[4] = ~c[4];
+        u[5] = ~(c[4] | (c[3] & c[2] & c[1] & c[0]));
+        u[6] = ~(c[4] | (c[3] & c[2] & c[1]));
+    }
+    // The lane's own three prefix bases: the base-4 digits of the lane index.
+    uint32_t ch[3], cl[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const uint32_t b = (ln >> (2 * (2 - q))) & 3u;
+        ch[q] = 0u - (b >> 1);
+        cl[q] = 0u - (b & 1u);
+    }
+    uint32_t found[K], top[N1];
+#pragma unroll
+    for (int c = 0; c < K; ++c) found[c] = 0u;
+#pragma unroll
+    for (int c = 0; c < N1; ++c) top[c] = 0u;
+    // Per window group only positions Q..L-1 are read: 6 high-plane words
+    // and 6 low-plane words, in SGPRs, the next group's loaded while the
+    // selection tree runs (as in scan_group).
+    uint32_t w[12];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        w[i] = ((__attribute__((address_space(4))) const volatile uint32_t*)W)[Q + i];
+        w[6 + i] = ((__attribute__((address_space(4))) const volatile uint32_t*)W)[L + Q + i];
+    }
+    for (uint32_t gi = 0; gi < groups; ++gi) {
+        uint32_t uu[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            uu[k] = static_cast<uint32_t>(
+                __builtin_amdgcn_ds_bpermute(static_cast<int>(gi << 2), static_cast<int>(u[k])));
+        uint32_t m[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) m[q] = (w[q] ^ ch[q]) | (w[6 + q] ^ cl[q]);
+        uint32_t v1[6], v2[5], t[4];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v1[k] = bop3<kMux>(m[0], uu[k + 1], uu[k]);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) v2[k] = bop3<kMux>(m[1], v1[k + 1], v1[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[k] = bop3<kMux>(m[2], v2[k + 1], v2[k]);
+        uint32_t sv[S][4];
+#pragma unroll
+        for (int q = 0; q < S; ++q) suffix_vectors(w[3 + q], w[9 + q], sv[q]);
+#pragma unroll
+        for (int k = 0; k <= S; ++k) asm volatile("" : "+v"(t[k]));
+        W += gi + 1 < groups ? 2 * L : 0;
+        asm volatile("" : "+s"(W));
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            w[i] = W[Q + i];
+            w[6 + i] = W[L + Q + i];
+        }
+        select_accumulate<S>(t, sv, found, top);
+    }
+    return group_pass<S>(found, top) & alive;
+}
+
+// Dispatch on P (wave-uniform, 3..13).
+__device__ __forceinline__ uint64_t scan_group_s0_any(uint32_t P, cu32* W, uint32_t groups,
+                                                      uint32_t shared, uint32_t lane, int d,
+                                                      uint64_t alive) {
+    switch (P) {
+        case 3: return scan_group_s0<3>(W, groups, shared, lane, d, alive);
+        case 4: return scan_group_s0<4>(W, groups, shared, lane, d, alive);
+        case 5: return scan_group_s0<5>(W, groups, shared, lane, d, alive);
+        case 6: return scan_group_s0<6>(W, groups, shared, lane, d, alive);
+        case 7: return scan_group_s0<7>(W, groups, shared, lane, d, alive);
+        case 8: return scan_group_s0<8>(W, groups, shared, lane, d, alive);
+        case 9: return scan_group_s0<9>(W, groups, shared, lane, d, alive);
+        case 10: return scan_group_s0<10>(W, groups, shared, lane, d, alive);
+        case 11: return scan_group_s0<11>(W, groups, shared, lane, d, alive);
+        case 12: return scan_group_s0<12>(W, groups, shared, lane, d, alive);
+        default: return scan_group_s0<13>(W, groups, shared, lane, d, alive);
+    }
+}
+
 // One sequence scan for one candidate per lane: whether some window is
 // within d of the l-mer `code` (motif code).  All L positions are counted
 // per lane by the carry-save tree of scan_group, with no selection tree; the
@@ -421,6 +553,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         uint32_t s, prefix = 0;
         Mask alive = 0;
         bool single = false;
+        bool fresh = false;     // a stage-0 batch of 64 groups aligned to 64
         const uint64_t full = ballot((qc & 0xffffu) >= 64u);
         const uint64_t sfull = kSingles ? ballot(qc >= (64u << 16)) : 0;
         if (full | sfull) {
@@ -460,6 +593,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             const uint64_t g = next + lane;
             prefix = static_cast<uint32_t>(g);
             alive = g < end ? kAll : static_cast<Mask>(0);
+            fresh = (next & 63u) == 0;
             next += 64;
         } else {
             if (stash == kNone && more) {
@@ -606,7 +740,15 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         }
 
         // One sequence scan for 64 groups.
-        const Mask pass = scan_group_any<S>(P, W + s * row, groups, prefix, d, alive);
+        Mask pass;
+        if constexpr (S == 3) {
+            if (fresh && P >= 3u && groups <= 64u)
+                pass = scan_group_s0_any(P, W, groups, uni(prefix >> 6), lane, d, alive);
+            else
+                pass = scan_group_any<S>(P, W + s * row, groups, prefix, d, alive);
+        } else {
+            pass = scan_group_any<S>(P, W + s * row, groups, prefix, d, alive);
+        }
         visits += static_cast<uint32_t>(__builtin_popcountll(static_cast<uint64_t>(alive)));
         ++batches;
         const bool keep = pass != 0;
