@@ -255,6 +255,7 @@ def bench_plain(args):
         "seq_visits": st["seq_visits"],
         "window_compares": wc,
         "candidate_slots": st["candidate_slots"],
+        "batches": st["batches"],
         "slot_efficiency": st["seq_visits"] / max(1, st["candidate_slots"]),
         "variant": nat.VARIANT_NAMES[st["variant"]],
         "motifs": int(codes.size),

@@ -418,16 +418,18 @@ int query_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, 
     if (variant == PMS_VARIANT_LANE) {
         per_wave = static_cast<size_t>(pms::queue_words(max_n, variant) + PMS_OUTBUF) * 4;
     } else {
-        const uint32_t entry = pms::stage_queue_words(variant == PMS_VARIANT_GROUP64 ? 3 : 2);
+        const int suffix = variant == PMS_VARIANT_GROUP64 ? 3 : 2;
+        const uint32_t entry = pms::stage_queue_words(suffix);
+        const uint32_t fixed = pms::wave_fixed_words(suffix);
         hipFuncAttributes attr;
         PMS_HIP(hipFuncGetAttributes(&attr, fn));
         const int vgprs = std::max(attr.numRegs, 8);
         const int per_simd = std::max(1, std::min(8, 512 / ((vgprs + 7) / 8 * 8)));
         const size_t budget = c.lds_per_cu / (4 * static_cast<size_t>(per_simd));
-        const size_t fit = budget / 4 > PMS_OUTBUF ? (budget / 4 - PMS_OUTBUF) / entry : 0;
+        const size_t fit = budget / 4 > fixed ? (budget / 4 - fixed) / entry : 0;
         lds_stages = std::min<uint32_t>(stages, static_cast<uint32_t>(fit));
         gq_words = (stages - lds_stages) * entry;
-        per_wave = static_cast<size_t>(lds_stages * entry + PMS_OUTBUF) * 4;
+        per_wave = static_cast<size_t>(lds_stages * entry + fixed) * 4;
     }
     uint32_t w = cfg.wg_waves;
     if (variant == PMS_VARIANT_GROUP64) w = std::min<uint32_t>(w, PMS_GROUP64_MAX_THREADS / 64);

@@ -302,36 +302,47 @@ __device__ __forceinline__ typename MaskOf<S>::type scan_group_any(
     }
 }
 
-// Stage-0 scan of 64 consecutive groups that start on a multiple of 64: the
-// lanes then share their first Q = P - 3 prefix bases (`shared`, the group
-// number over 64) and differ only in the last three, which are the base-4
-// digits of the lane index.
-//  * Once per call, lane j counts the shared positions' mismatches for
-//    window group j (carry-save, bias 19 - d, c' = c + 19 - d < 32) and keeps
-//    the thresholds U_k = [c <= d - k], k = 0..6, as comparisons of c' with
-//    the constants 19 - k.
+// Scan of 64 groups whose prefixes fall into at most 64 / groups blocks of
+// 64 consecutive groups: the groups of one block share their first Q = P - 3
+// bases (the block number, prefix >> 6) and differ only in the last three
+// (prefix & 63).  A stage-0 batch aligned to 64 groups is one block; a
+// stage-1 batch, the top of a queue fed by consecutive stage-0 batches,
+// usually two or three.
+//  * Once per call, table lane b*groups + j (block b, window group j) counts
+//    the block's shared-position mismatches for window group j (carry-save,
+//    bias 19 - d, c' = c + 19 - d < 32) and keeps the thresholds
+//    U_k = [c <= d - k], k = 0..6, as comparisons of c' with the constants
+//    19 - k.  Lanes j < groups also write window group j's suffix mismatch
+//    vectors into the wavefront's LDS table `svt`.
 //  * Per 32 windows every lane fetches U_0..U_6 of the current window group
-//    from lane gi (ds_bpermute) and walks them through its own three prefix
-//    positions with the selection recursion of the suffix:
+//    from its block's table lane (ds_bpermute) and walks them through its
+//    own three prefix positions with the selection recursion of the suffix:
 //      V_1[k] = m_1 ? U[k+1] : U[k]    (k = 0..5)
 //      V_2[k] = m_2 ? V_1[k+1] : V_1[k] (k = 0..4)
 //      T[k]   = m_3 ? V_2[k+1] : V_2[k] (k = 0..3)
 //    so T[k] = [mismatches over the whole prefix <= d - k], as in scan_group.
-// The prefix count over Q positions is thus done once per call instead of
-// once per window group per lane, and no prefix word of the shared positions
-// is read per iteration.  Requires 3 <= P <= 13 and groups <= 64.
+// The prefix count over Q positions is thus done once per call and block
+// instead of once per window group per lane, no word of the shared positions
+// is read per iteration, and the suffix vectors come from LDS (three
+// broadcast reads straight into VGPRs) instead of being moved from SGPRs.
+// Arguments, per lane: kv, tj = the block and window group this lane builds
+// thresholds for (tj >= groups: none); src = first table lane of the lane's
+// own block; low = prefix & 63.  Requires 3 <= P <= 13 and 12 * groups <=
+// PMS_SVT_WORDS.
 template <int P>
-__device__ __forceinline__ uint64_t scan_group_s0(cu32* W, uint32_t groups, uint32_t shared,
-                                                  uint32_t lane, int d, uint64_t alive) {
+__device__ __forceinline__ uint64_t scan_group_shared(cu32* W, uint32_t groups, uint32_t kv,
+                                                      uint32_t tj, uint32_t src, uint32_t low,
+                                                      int d, uint64_t alive,
+                                                      uint32_t* __restrict__ svt) {
     constexpr int S = 3;
     constexpr int L = P + S;
     constexpr int Q = P - 3;           // shared prefix positions
     constexpr int K = 64;
     constexpr int N1 = K / 4;
-    // Lane-derived values (the row offset below, the lane's prefix masks)
-    // are rebuilt per call: hoisted out of the persistent loop, they would
-    // hold registers through every other path as well.
-    uint32_t ln = lane;
+    // The lane index is rebuilt per call: hoisted out of the persistent
+    // loop, values derived from it would hold registers through every other
+    // path as well.
+    uint32_t ln = lane_id();
     asm volatile("" : "+v"(ln));
     uint32_t u[7];
     {
@@ -342,12 +353,23 @@ __device__ __forceinline__ uint64_t scan_group_s0(cu32* W, uint32_t groups, uint
         uint32_t m[Q > 0 ? Q : 1];
 #pragma unroll
         for (int p = 0; p < (Q > 0 ? Q : 1); ++p) m[p] = 0u;
-        if (ln < groups) {
-            const uint32_t* row = (const uint32_t*)(W) + ln * (2u * L);
+        if (tj < groups) {
+            const uint32_t* row = (const uint32_t*)(W) + tj * (2u * L);
 #pragma unroll
             for (int p = 0; p < Q; ++p) {
-                const uint32_t b = (shared >> (2 * (Q - 1 - p))) & 3u;
+                const uint32_t b = (kv >> (2 * (Q - 1 - p))) & 3u;
                 m[p] = (row[p] ^ (0u - (b >> 1))) | (row[L + p] ^ (0u - (b & 1u)));
+            }
+        }
+        if (ln < groups) {
+            // This window group's suffix mismatch vectors (A, C, G, T at
+            // each suffix position) into the wavefront's table.
+            const uint32_t* row = (const uint32_t*)(W) + ln * (2u * L);
+            uint4* dst = reinterpret_cast<uint4*>(svt + ln * 12u);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const uint32_t h = row[P + q], lo = row[L + P + q];
+                dst[q] = make_uint4(h | lo, h | ~lo, ~h | lo, ~(h & lo));
             }
         }
         uint32_t c[5];
@@ -360,11 +382,11 @@ __device__ __forceinline__ uint64_t scan_group_s0(cu32* W, uint32_t groups, uint
         u[5] = ~(c[4] | (c[3] & c[2] & c[1] & c[0]));
         u[6] = ~(c[4] | (c[3] & c[2] & c[1]));
     }
-    // The lane's own three prefix bases: the base-4 digits of the lane index.
+    // The lane's own last three prefix bases.
     uint32_t ch[3], cl[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const uint32_t b = (ln >> (2 * (2 - q))) & 3u;
+        const uint32_t b = (low >> (2 * (2 - q))) & 3u;
         ch[q] = 0u - (b >> 1);
         cl[q] = 0u - (b & 1u);
     }
@@ -373,24 +395,39 @@ __device__ __forceinline__ uint64_t scan_group_s0(cu32* W, uint32_t groups, uint
     for (int c = 0; c < K; ++c) found[c] = 0u;
 #pragma unroll
     for (int c = 0; c < N1; ++c) top[c] = 0u;
-    // Per window group only positions Q..L-1 are read: 6 high-plane words
-    // and 6 low-plane words, in SGPRs, the next group's loaded while the
-    // selection tree runs (as in scan_group).
-    uint32_t w[12];
+    // Per window group the loop reads the lane positions' words (3 high, 3
+    // low plane, in SGPRs, the next group's loaded while the selection tree
+    // runs, as in scan_group) and the suffix vectors from the table (three
+    // broadcast LDS reads straight into VGPRs: no v_mov from SGPRs).
+    uint32_t w[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 3; ++i) {
         w[i] = ((__attribute__((address_space(4))) const volatile uint32_t*)W)[Q + i];
-        w[6 + i] = ((__attribute__((address_space(4))) const volatile uint32_t*)W)[L + Q + i];
+        w[3 + i] = ((__attribute__((address_space(4))) const volatile uint32_t*)W)[L + Q + i];
     }
+    const uint4* sp = reinterpret_cast<const uint4*>(svt);
     for (uint32_t gi = 0; gi < groups; ++gi) {
+        // LDS traffic first (thresholds, suffix vectors): LDS and scalar
+        // loads share one counter, so these must be complete before the
+        // next group's scalar loads are issued below, or the wait for them
+        // would also wait for those loads.
         uint32_t uu[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k)
-            uu[k] = static_cast<uint32_t>(
-                __builtin_amdgcn_ds_bpermute(static_cast<int>(gi << 2), static_cast<int>(u[k])));
+            uu[k] = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(
+                static_cast<int>((src + gi) << 2), static_cast<int>(u[k])));
+        uint32_t sv[S][4];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const uint4 v = sp[gi * 3u + q];
+            sv[q][0] = v.x;
+            sv[q][1] = v.y;
+            sv[q][2] = v.z;
+            sv[q][3] = v.w;
+        }
         uint32_t m[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) m[q] = (w[q] ^ ch[q]) | (w[6 + q] ^ cl[q]);
+        for (int q = 0; q < 3; ++q) m[q] = (w[q] ^ ch[q]) | (w[3 + q] ^ cl[q]);
         uint32_t v1[6], v2[5], t[4];
 #pragma unroll
         for (int k = 0; k < 6; ++k) v1[k] = bop3<kMux>(m[0], uu[k + 1], uu[k]);
@@ -398,17 +435,18 @@ __device__ __forceinline__ uint64_t scan_group_s0(cu32* W, uint32_t groups, uint
         for (int k = 0; k < 5; ++k) v2[k] = bop3<kMux>(m[1], v1[k + 1], v1[k]);
 #pragma unroll
         for (int k = 0; k < 4; ++k) t[k] = bop3<kMux>(m[2], v2[k + 1], v2[k]);
-        uint32_t sv[S][4];
-#pragma unroll
-        for (int q = 0; q < S; ++q) suffix_vectors(w[3 + q], w[9 + q], sv[q]);
 #pragma unroll
         for (int k = 0; k <= S; ++k) asm volatile("" : "+v"(t[k]));
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) asm volatile("" : "+v"(sv[q][b]));
         W += gi + 1 < groups ? 2 * L : 0;
         asm volatile("" : "+s"(W));
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < 3; ++i) {
             w[i] = W[Q + i];
-            w[6 + i] = W[L + Q + i];
+            w[3 + i] = W[L + Q + i];
         }
         select_accumulate<S>(t, sv, found, top);
     }
@@ -416,21 +454,22 @@ __device__ __forceinline__ uint64_t scan_group_s0(cu32* W, uint32_t groups, uint
 }
 
 // Dispatch on P (wave-uniform, 3..13).
-__device__ __forceinline__ uint64_t scan_group_s0_any(uint32_t P, cu32* W, uint32_t groups,
-                                                      uint32_t shared, uint32_t lane, int d,
-                                                      uint64_t alive) {
+__device__ __forceinline__ uint64_t scan_group_shared_any(uint32_t P, cu32* W, uint32_t groups,
+                                                          uint32_t kv, uint32_t tj, uint32_t src,
+                                                          uint32_t low, int d, uint64_t alive,
+                                                          uint32_t* svt) {
     switch (P) {
-        case 3: return scan_group_s0<3>(W, groups, shared, lane, d, alive);
-        case 4: return scan_group_s0<4>(W, groups, shared, lane, d, alive);
-        case 5: return scan_group_s0<5>(W, groups, shared, lane, d, alive);
-        case 6: return scan_group_s0<6>(W, groups, shared, lane, d, alive);
-        case 7: return scan_group_s0<7>(W, groups, shared, lane, d, alive);
-        case 8: return scan_group_s0<8>(W, groups, shared, lane, d, alive);
-        case 9: return scan_group_s0<9>(W, groups, shared, lane, d, alive);
-        case 10: return scan_group_s0<10>(W, groups, shared, lane, d, alive);
-        case 11: return scan_group_s0<11>(W, groups, shared, lane, d, alive);
-        case 12: return scan_group_s0<12>(W, groups, shared, lane, d, alive);
-        default: return scan_group_s0<13>(W, groups, shared, lane, d, alive);
+        case 3: return scan_group_shared<3>(W, groups, kv, tj, src, low, d, alive, svt);
+        case 4: return scan_group_shared<4>(W, groups, kv, tj, src, low, d, alive, svt);
+        case 5: return scan_group_shared<5>(W, groups, kv, tj, src, low, d, alive, svt);
+        case 6: return scan_group_shared<6>(W, groups, kv, tj, src, low, d, alive, svt);
+        case 7: return scan_group_shared<7>(W, groups, kv, tj, src, low, d, alive, svt);
+        case 8: return scan_group_shared<8>(W, groups, kv, tj, src, low, d, alive, svt);
+        case 9: return scan_group_shared<9>(W, groups, kv, tj, src, low, d, alive, svt);
+        case 10: return scan_group_shared<10>(W, groups, kv, tj, src, low, d, alive, svt);
+        case 11: return scan_group_shared<11>(W, groups, kv, tj, src, low, d, alive, svt);
+        case 12: return scan_group_shared<12>(W, groups, kv, tj, src, low, d, alive, svt);
+        default: return scan_group_shared<13>(W, groups, kv, tj, src, low, d, alive, svt);
     }
 }
 
@@ -527,8 +566,9 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
     const uint32_t wave = uni(threadIdx.x >> 6);
-    uint32_t* const qp = lds + wave * (lds_stages * kStageWords + PMS_OUTBUF);
+    uint32_t* const qp = lds + wave * (lds_stages * kStageWords + pms::wave_fixed_words(S));
     uint32_t* const ob = qp + lds_stages * kStageWords;
+    uint32_t* const svt = ob + PMS_OUTBUF;   // S = 3: stage-0 suffix vectors
     const uint32_t gwave = blockIdx.x * uni(blockDim.x >> 6) + wave;
     uint32_t* const gw = gq + static_cast<size_t>(gwave) * gq_words;
     const uint32_t stages_cap = lds_stages + gq_words / kStageWords;
@@ -553,7 +593,6 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         uint32_t s, prefix = 0;
         Mask alive = 0;
         bool single = false;
-        bool fresh = false;     // a stage-0 batch of 64 groups aligned to 64
         const uint64_t full = ballot((qc & 0xffffu) >= 64u);
         const uint64_t sfull = kSingles ? ballot(qc >= (64u << 16)) : 0;
         if (full | sfull) {
@@ -593,7 +632,6 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             const uint64_t g = next + lane;
             prefix = static_cast<uint32_t>(g);
             alive = g < end ? kAll : static_cast<Mask>(0);
-            fresh = (next & 63u) == 0;
             next += 64;
         } else {
             if (stash == kNone && more) {
@@ -742,10 +780,45 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         // One sequence scan for 64 groups.
         Mask pass;
         if constexpr (S == 3) {
-            if (fresh && P >= 3u && groups <= 64u)
-                pass = scan_group_s0_any(P, W, groups, uni(prefix >> 6), lane, d, alive);
-            else
+            // Blocks of 64 consecutive groups among the live lanes, each
+            // given `groups` table lanes; the shared-prefix scan applies when
+            // they all fit (one block for an aligned stage-0 batch).
+            // (Counted first with wave-uniform values only, then the
+            // per-lane block data inside the branch that uses it: computed
+            // ahead of the branch, it cost the general scan registers.)
+            bool blocks_fit = false;
+            if (P >= 3u && groups * 12u <= PMS_SVT_WORDS) {
+                const uint32_t kmax = 64u / groups;
+                uint64_t todo = ballot(alive != 0);
+                for (uint32_t k = 0; todo != 0 && k < kmax; ++k) {
+                    const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
+                        static_cast<int>(prefix >> 6), static_cast<int>(__builtin_ctzll(todo))));
+                    todo &= ~ballot((prefix >> 6) == v);
+                }
+                blocks_fit = todo == 0;
+            }
+            if (blocks_fit) {
+                const uint32_t kmax = 64u / groups;
+                const uint32_t hi = prefix >> 6;
+                uint32_t kv = 0, tj = 64u, src = 0;
+                uint64_t todo = ballot(alive != 0);
+                for (uint32_t k = 0; todo != 0 && k < kmax; ++k) {
+                    const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
+                        static_cast<int>(hi), static_cast<int>(__builtin_ctzll(todo))));
+                    const bool mine = hi == v;
+                    todo &= ~ballot(mine);
+                    const uint32_t b = k * groups;
+                    if (mine) src = b;
+                    if (lane - b < groups) {
+                        kv = v;
+                        tj = lane - b;
+                    }
+                }
+                pass = scan_group_shared_any(P, W + s * row, groups, kv, tj, src, prefix & 63u, d,
+                                             alive, svt);
+            } else {
                 pass = scan_group_any<S>(P, W + s * row, groups, prefix, d, alive);
+            }
         } else {
             pass = scan_group_any<S>(P, W + s * row, groups, prefix, d, alive);
         }
@@ -905,7 +978,8 @@ hipError_t launch_search_group(const pms_dev_instance* insts, const pms_work_ite
                                const GroupQueues& q, uint32_t grid, uint32_t wg_waves,
                                hipStream_t stream, int suffix) {
     const size_t lds = static_cast<size_t>(wg_waves) *
-                       (q.lds_stages * stage_queue_words(suffix) + PMS_OUTBUF) * sizeof(uint32_t);
+                       (q.lds_stages * stage_queue_words(suffix) + wave_fixed_words(suffix)) *
+                       sizeof(uint32_t);
     if (suffix == 3)
         hipLaunchKernelGGL(pms_search_group64_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream,
                            insts, work, n_work, state, ctr, q.lds_stages, q.gq, q.gq_words);

@@ -105,6 +105,17 @@ constexpr uint32_t stage_queue_words(int suffix) {
     return suffix == 3 ? 3u * PMS_QCAP + PMS_SCAP : 2u * PMS_QCAP;
 }
 
+// Suffix-vector table of the 64-candidate kernel's stage-0 scans, per
+// wavefront: 12 words per window group (4 mismatch vectors for each of the
+// three suffix positions), so rows of up to 42 window groups use it.
+#define PMS_SVT_WORDS 512u
+
+// LDS words per wavefront of a grouped launch besides its stage queues:
+// the survivor staging buffer and (suffix 3) the suffix-vector table.
+constexpr uint32_t wave_fixed_words(int suffix) {
+    return PMS_OUTBUF + (suffix == 3 ? PMS_SVT_WORDS : 0u);
+}
+
 // Words of stage queues one wavefront needs for instances of up to max_n
 // sequences.  variant: LANE keeps one uint32 candidate per slot; the grouped
 // variants as in stage_queue_words.
