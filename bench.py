@@ -256,6 +256,7 @@ def bench_plain(args):
         "window_compares": wc,
         "candidate_slots": st["candidate_slots"],
         "batches": st["batches"],
+        "single_batches": st["single_batches"],
         "slot_efficiency": st["seq_visits"] / max(1, st["candidate_slots"]),
         "variant": nat.VARIANT_NAMES[st["variant"]],
         "motifs": int(codes.size),

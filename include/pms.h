@@ -230,6 +230,7 @@ typedef struct {
                                 the launch (0 for device-level calls) */
     double host_finish_ms;   /* host-level calls: copy-back, sort and capacity handling
                                 after the launch, reruns included (0 for device-level) */
+    uint64_t single_batches; /* of `batches`: GROUP64 scans of one candidate per lane */
 } pms_stats;
 
 int pms_last_stats(pms_stats* out);

@@ -773,6 +773,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     c.last.seq_visits = visits;
     c.last.window_compares = wcmp;
     c.last.batches = ctr->batches;
+    c.last.single_batches = ctr->single_batches;
     c.last.candidate_slots = candidate_slots(*ctr, b.variant);
     c.last.reruns = 0;
     // Step a7.  Every instance's codes go to its segment of one pinned
@@ -1356,6 +1357,7 @@ int pms_last_stats(pms_stats* out) {
             c.last.seq_visits = st.visits;
             c.last.window_compares = st.visits * static_cast<uint64_t>(c.dv_nw);
             c.last.batches = ctr.batches;
+            c.last.single_batches = ctr.single_batches;
             c.last.candidate_slots = candidate_slots(ctr, c.dv_variant);
         }
         c.last_pending = false;

@@ -82,7 +82,8 @@ class Stats(ctypes.Structure):
                 ("grid", ctypes.c_uint32), ("wg_waves", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("reruns", ctypes.c_uint32),
                 ("variant", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("host_prep_ms", ctypes.c_double), ("host_finish_ms", ctypes.c_double)]
+                ("host_prep_ms", ctypes.c_double), ("host_finish_ms", ctypes.c_double),
+                ("single_batches", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))

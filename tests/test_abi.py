@@ -39,7 +39,7 @@ def test_struct_layouts_match_header(tmp_path):
         "pms_config": ["chunk", "wg_waves", "wgs_per_cu", "tail_split", "variant"],
         "pms_stats": ["kernel_ms", "windows_ms", "seq_visits", "batches", "window_compares",
                       "candidate_slots", "grid", "wg_waves", "chunk", "reruns", "variant",
-                      "host_prep_ms", "host_finish_ms"],
+                      "host_prep_ms", "host_finish_ms", "single_batches"],
         "pms_dev_instance": ["windows", "out", "out_cap", "n", "nw_stride", "l", "d"],
         "pms_work_item": ["begin", "len", "inst"],
         "pms_dev_state": ["count", "visits", "t_done", "items_left"],
