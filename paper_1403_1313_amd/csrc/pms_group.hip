@@ -568,7 +568,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     const uint32_t wave = uni(threadIdx.x >> 6);
     uint32_t* const qp = lds + wave * (lds_stages * kStageWords + pms::wave_fixed_words(S));
     uint32_t* const ob = qp + lds_stages * kStageWords;
-    uint32_t* const svt = ob + PMS_OUTBUF;   // S = 3: stage-0 suffix vectors
+    uint32_t* const svt = ob + PMS_OUTBUF;   // S = 3: shared-prefix scans' suffix vectors
     const uint32_t gwave = blockIdx.x * uni(blockDim.x >> 6) + wave;
     uint32_t* const gw = gq + static_cast<size_t>(gwave) * gq_words;
     const uint32_t stages_cap = lds_stages + gq_words / kStageWords;

@@ -105,7 +105,7 @@ constexpr uint32_t stage_queue_words(int suffix) {
     return suffix == 3 ? 3u * PMS_QCAP + PMS_SCAP : 2u * PMS_QCAP;
 }
 
-// Suffix-vector table of the 64-candidate kernel's stage-0 scans, per
+// Suffix-vector table of the 64-candidate kernel's shared-prefix scans, per
 // wavefront: 12 words per window group (4 mismatch vectors for each of the
 // three suffix positions), so rows of up to 42 window groups use it.
 #define PMS_SVT_WORDS 512u
