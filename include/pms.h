@@ -181,11 +181,13 @@ enum pms_input_flag {
 
 /* Shape of the persistent search launch.  Zero fields mean "default". */
 typedef struct {
-    uint32_t chunk;        /* candidates per work item (multiple of 64) */
+    uint32_t chunk;        /* least candidates per work item (multiple of 64); items are
+                              rounded up to multiples of 4096 candidates for l >= 6 */
     uint32_t wg_waves;     /* 64-lane wavefronts per workgroup (1..16) */
     uint32_t wgs_per_cu;   /* resident workgroups per compute unit (0 = as many as fit) */
     uint32_t tail_split;   /* work items of the last tail_split/64 of each instance are
-                              cut 4x smaller, so the launch ends evenly (0..64) */
+                              cut 4x smaller, so the launch ends evenly (0..64; the
+                              default, 0, splits nothing) */
     uint32_t variant;      /* pms_variant */
 } pms_config;
 
