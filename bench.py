@@ -318,8 +318,9 @@ def bench_copy(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the search shards "
-              "by candidate ranges across GPUs, which this build does not launch.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the search would "
+              "shard by candidate ranges across GPUs, which this program does not launch.",
+              file=sys.stderr)
         return 2
     if args.mode == "plain":
         return bench_plain(args)

@@ -39,8 +39,13 @@ def bench_batched(args):
     insts = [s.make() for s in specs]
     work = [(i.seqs, i.l, i.d) for i in insts]
     caps = [1 << 21] * len(insts)
-    cache = os.environ.get("PMS_AUTOTUNE_CACHE") or os.path.join(ROOT, "gpurun_out", "autotune.json")
-    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    cache = os.environ.get("PMS_AUTOTUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_1403_1313_amd", "autotune.json")
+    try:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+    except OSError:
+        import tempfile
+        cache = os.path.join(tempfile.gettempdir(), "paper_1403_1313_amd_autotune.json")
     nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant])
     t0 = time.perf_counter()
     tuned = nat.autotune(20, 650, 13, 4, cache)
