@@ -369,6 +369,29 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
 int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
                   uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count, void* stream);
 
+/*
+ * pms_solve_dev_noalloc -- pms_solve_dev for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and ordering
+ * rules as pms_solve_dev; the caller still owns dev_seqs, dev_out and
+ * dev_count.  Everything else the solve needs (window table, instance and
+ * work records, stage-queue workspace) lives in one fixed array of
+ * PMS_NOALLOC_SCRATCH_BYTES per device, held by the library until the process
+ * ends; the records are rebuilt and the counters cleared on the device by
+ * every call, so the call makes no hipMalloc, hipFree, host-to-device copy or
+ * memset.  All calls on one device share that array: calls that overlap on
+ * the device (two streams, or two threads without ordering) race and give
+ * wrong results.  When the stage queues of a full-occupancy launch do not fit
+ * beside the tables, fewer workgroups are launched (same result, slower);
+ * PMS_ERR_INVALID when the tables and one workgroup's queues exceed the array
+ * (not reachable within PMS_MAX_N / PMS_MAX_T today).  pms_last_stats reports
+ * only the launch shape after this call (no timings or counters).
+ */
+#define PMS_NOALLOC_SCRATCH_BYTES (128u << 20)
+int pms_solve_dev_noalloc(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
+                          uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

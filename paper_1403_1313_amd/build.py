@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpms.so")
 SOURCES = [os.path.join(CSRC, "pms_kernels.hip"), os.path.join(CSRC, "pms_group.hip"),
            os.path.join(CSRC, "pms_nbhd.hip"), os.path.join(CSRC, "pms_probe.hip"),
-           os.path.join(CSRC, "pms_api.hip")]
+           os.path.join(CSRC, "pms_noalloc.hip"), os.path.join(CSRC, "pms_api.hip")]
 ARCH = os.environ.get("PMS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

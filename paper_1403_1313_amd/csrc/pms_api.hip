@@ -292,7 +292,10 @@ struct Shape2 {
 
 struct Ctx {
     std::mutex mu;
-    bool ready = false;
+    bool ready = false;            // stream and events created (init_ctx)
+    bool dev_ready = false;        // device properties and scratch address (init_device)
+    void* scratch = nullptr;       // this device's fixed scratch (device address)
+    size_t scratch_bytes = 0;
     int device = 0;
     int cus = 0;
     size_t lds_per_block = 65536;
@@ -355,8 +358,10 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 // About 32 work items per wavefront the device can hold resident.
 uint64_t target_items(const Ctx& c) { return static_cast<uint64_t>(std::max(c.cus, 1)) * 16u * 32u; }
 
-int init_ctx(Ctx& c) {
-    if (c.ready) return PMS_OK;
+// Device properties and the address of this device's copy of the fixed
+// scratch (pms_solve_dev_noalloc): no stream, event or memory is created.
+int init_device(Ctx& c) {
+    if (c.dev_ready) return PMS_OK;
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || count == 0)
@@ -374,6 +379,15 @@ int init_ctx(Ctx& c) {
     c.lds_per_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
                                                          : prop.sharedMemPerBlock;
     c.arch = prop.gcnArchName;
+    PMS_HIP(pms::noalloc_scratch(&c.scratch, &c.scratch_bytes));
+    c.dev_ready = true;
+    return PMS_OK;
+}
+
+int init_ctx(Ctx& c) {
+    if (c.ready) return PMS_OK;
+    PMS_TRY(init_device(c));
+    PMS_HIP(hipSetDevice(c.device));
     PMS_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
     for (auto& e2 : c.ev) PMS_HIP(hipEventCreate(&e2));
     PMS_HIP(hipEventCreateWithFlags(&c.dv_copied, hipEventDisableTiming));
@@ -384,13 +398,10 @@ int init_ctx(Ctx& c) {
 
 int query_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, Shape2* out);
 
-// Workgroup shape, grid and queue placement for a search launch.  The
-// grouped kernels keep as many stage queues in LDS as the occupancy their
-// registers allow leaves room for, and the rest in `ws` (grown as needed).
-int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, DevBuf& ws,
-                 Shape2* out) {
-    // The kernel attribute and occupancy queries depend only on these four
-    // values; their answers are kept for later launches.
+// Workgroup shape, grid and queue placement for a search launch (no
+// workspace attached).  The kernel attribute and occupancy queries depend
+// only on (variant, max_n, wg_waves, wgs_per_cu); their answers are kept.
+int cached_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, Shape2* out) {
     const uint64_t key = (static_cast<uint64_t>(variant) << 48) |
                          (static_cast<uint64_t>(max_n) << 32) |
                          (static_cast<uint64_t>(cfg.wg_waves) << 16) | cfg.wgs_per_cu;
@@ -401,6 +412,14 @@ int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant,
         hit = c.shapes.emplace(key, sh).first;
     }
     *out = hit->second;
+    return PMS_OK;
+}
+
+// As cached_shape, with the stage queues that do not fit in LDS placed in
+// `ws` (grown as needed).
+int launch_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, DevBuf& ws,
+                 Shape2* out) {
+    PMS_TRY(cached_shape(c, cfg, max_n, variant, out));
     if (out->gq.gq_words) {
         PMS_TRY(ws.ensure(static_cast<size_t>(out->grid) * out->waves * out->gq.gq_words * 4));
         out->gq.gq = ws.as<uint32_t>();
@@ -447,6 +466,28 @@ int query_shape(Ctx& c, const pms_config& cfg, int32_t max_n, uint32_t variant, 
     return PMS_OK;
 }
 
+// Item sizes of one instance that gets `share` of a launch's work items.
+// Items start on multiples of 4096 candidates where the space allows (64
+// groups of 64: the grouped kernel's stage-0 batches then share all but three
+// prefix bases).  Items before head_end hold `size` candidates, the rest
+// `small`.
+struct ItemPlan {
+    uint64_t total, size, small, head_end;
+};
+
+ItemPlan item_plan(const Shape& s, double share, const pms_config& cfg, uint64_t target_items) {
+    ItemPlan p;
+    p.total = 1ull << (2 * s.l);
+    const uint64_t want_items = std::max<uint64_t>(1, static_cast<uint64_t>(share * target_items));
+    const uint64_t unit = p.total >= 4096 ? 4096 : 64;
+    uint64_t size = std::max<uint64_t>(cfg.chunk, (p.total + want_items - 1) / want_items);
+    p.size = std::min<uint64_t>(align_up(size, unit), 1ull << 30);
+    const uint64_t tail = align_up(p.total * cfg.tail_split / 64, unit);
+    p.head_end = p.total - std::min(tail, p.total);
+    p.small = std::max<uint64_t>(unit, align_up(p.size / 4, unit));
+    return p;
+}
+
 // Cuts each instance's candidate range into work items.  Instances go in
 // descending order of estimated work (longest first).  An instance receives a
 // number of items in proportion to its share of the launch's estimated work,
@@ -460,23 +501,12 @@ void build_work(Batch& b, const std::vector<int>& order, const std::vector<doubl
     double total_cost = 0;
     for (int i : order) total_cost += cost[i];
     for (int i : order) {
-        const Shape& s = b.shape[i];
-        const uint64_t total = 1ull << (2 * s.l);
         const double share = total_cost > 0 ? cost[i] / total_cost : 1.0;
-        const uint64_t want_items = std::max<uint64_t>(1, static_cast<uint64_t>(share * target_items));
-        // Items start on multiples of 4096 candidates where the space allows
-        // (64 groups of 64: the grouped kernel's stage-0 batches then share
-        // all but three prefix bases).
-        const uint64_t unit = total >= 4096 ? 4096 : 64;
-        uint64_t size = std::max<uint64_t>(cfg.chunk, (total + want_items - 1) / want_items);
-        size = std::min<uint64_t>(align_up(size, unit), 1ull << 30);
-        const uint64_t tail = align_up(total * cfg.tail_split / 64, unit);
-        const uint64_t head_end = total - std::min(tail, total);
-        const uint64_t small = std::max<uint64_t>(unit, align_up(size / 4, unit));
+        const ItemPlan p = item_plan(b.shape[i], share, cfg, target_items);
         uint64_t k = 0;
-        while (k < total) {
-            const uint64_t step = k < head_end ? size : small;
-            const uint64_t len = std::min<uint64_t>(step, total - k);
+        while (k < p.total) {
+            const uint64_t step = k < p.head_end ? p.size : p.small;
+            const uint64_t len = std::min<uint64_t>(step, p.total - k);
             b.work.push_back({k, static_cast<uint32_t>(len), static_cast<uint32_t>(i)});
             b.items_per_inst[i]++;
             k += len;
@@ -1522,6 +1552,99 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     c.dv_state_off = b.off_state;
     c.dv_ctr_off = b.off_ctr;
     c.dv_nw = t - l + 1;
+    return PMS_OK;
+}
+
+int pms_solve_dev_noalloc(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
+                          uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count,
+                          void* stream) {
+    g_last_error.clear();
+    if (!dev_seqs || !dev_count || (capacity > 0 && !dev_out))
+        return fail(PMS_ERR_INVALID, "NULL device pointer");
+    PMS_TRY(validate_shape(n, t, l, d));
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    PMS_TRY(init_device(c));
+    if (!c.scratch) return fail(PMS_ERR_DEVICE, "no scratch address for this device");
+    const pms_config cfg = c.cfg;
+    const Shape shape{n, t, l, d};
+    const uint32_t variant = choose_variant({shape}, cfg.variant);
+    const int32_t layout = variant == PMS_VARIANT_LANE ? PMS_LAYOUT_PLANES : PMS_LAYOUT_BITSLICED;
+    // The same items the host planner makes for one instance.
+    const ItemPlan ip = item_plan(shape, 1.0, cfg, target_items(c));
+    pms::NoallocLayout lay{};
+    lay.n = n;
+    lay.t = t;
+    lay.l = l;
+    lay.d = d;
+    lay.layout = layout;
+    lay.stride = window_stride(t, l, layout);
+    lay.size = ip.size;
+    lay.small = ip.small;
+    const uint64_t n_head = ip.head_end ? (ip.head_end + ip.size - 1) / ip.size : 0;
+    const uint64_t h = std::min(n_head * ip.size, ip.total);
+    const uint64_t n_small = h < ip.total ? (ip.total - h + ip.small - 1) / ip.small : 0;
+    lay.n_head = static_cast<uint32_t>(n_head);
+    lay.n_items = static_cast<uint32_t>(n_head + n_small);
+    size_t off = 0;
+    lay.off_win = off;
+    off = align_up(off + static_cast<size_t>(n) * lay.stride * 4, 256);
+    lay.off_inst = off;
+    off = align_up(off + sizeof(pms_dev_instance), 256);
+    lay.off_state = off;
+    off = align_up(off + sizeof(pms_dev_state), 256);
+    lay.off_ctr = off;
+    off = align_up(off + sizeof(pms_dev_counters), 256);
+    lay.off_bad = off;
+    off = align_up(off + sizeof(uint32_t), 256);
+    lay.off_jobs = off;
+    off = align_up(off + static_cast<size_t>(n) * sizeof(pms_win_job), 256);
+    lay.off_work = off;
+    off = align_up(off + static_cast<size_t>(lay.n_items) * sizeof(pms_work_item), 256);
+    // PMS_TEST_NOALLOC_CAP=<bytes> lowers the usable size (tests of the
+    // reduced grid and of the size error).
+    size_t avail = c.scratch_bytes;
+    if (const char* v = getenv("PMS_TEST_NOALLOC_CAP")) {
+        const long long k = atoll(v);
+        if (k > 0 && static_cast<size_t>(k) < avail) avail = static_cast<size_t>(k);
+    }
+    Shape2 sh;
+    PMS_TRY(cached_shape(c, cfg, n, variant, &sh));
+    const size_t per_wg = static_cast<size_t>(sh.waves) * sh.gq.gq_words * 4;
+    if (off > avail || (per_wg && avail - off < per_wg))
+        return fail(PMS_ERR_INVALID,
+                    "tables of this size (" + std::to_string(off + per_wg) +
+                        " bytes with one workgroup's stage queues) exceed the fixed scratch of " +
+                        std::to_string(avail) + " bytes");
+    if (per_wg) {
+        // Stage queues beyond LDS for every workgroup; with less room, fewer
+        // workgroups (the persistent search is exact with any grid).
+        sh.grid = static_cast<uint32_t>(std::min<size_t>(sh.grid, (avail - off) / per_wg));
+        sh.gq.gq = reinterpret_cast<uint32_t*>(static_cast<char*>(c.scratch) + off);
+        off += per_wg * sh.grid;
+    }
+    lay.off_gq = off - per_wg * sh.grid;
+    lay.bytes = off;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(c.scratch);
+    PMS_HIP(pms::launch_noalloc_setup(base, lay, dev_out, capacity, s));
+    PMS_HIP(pms::launch_windows(reinterpret_cast<const pms_win_job*>(base + lay.off_jobs), n, t,
+                                dev_seqs, reinterpret_cast<uint32_t*>(base + lay.off_win),
+                                reinterpret_cast<uint32_t*>(base + lay.off_bad), s));
+    PMS_HIP(launch_variant(variant, reinterpret_cast<const pms_dev_instance*>(base + lay.off_inst),
+                           reinterpret_cast<const pms_work_item*>(base + lay.off_work),
+                           lay.n_items, reinterpret_cast<pms_dev_state*>(base + lay.off_state),
+                           reinterpret_cast<pms_dev_counters*>(base + lay.off_ctr), sh, s));
+    PMS_HIP(pms::launch_noalloc_count(reinterpret_cast<const pms_dev_state*>(base + lay.off_state),
+                                      dev_count, s));
+    // No events or counters are kept for this call.
+    c.last = pms_stats{};
+    c.last.grid = sh.grid;
+    c.last.wg_waves = sh.waves;
+    c.last.chunk = cfg.chunk;
+    c.last.variant = variant;
+    c.last_pending = false;
+    c.dv_counters = false;
     return PMS_OK;
 }
 

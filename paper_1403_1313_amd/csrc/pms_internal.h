@@ -79,6 +79,24 @@ hipError_t launch_nbhd_verify(const uint32_t* cand, uint64_t count, const uint32
 
 const void* search_kernel_symbol();
 
+// Where one pms_solve_dev_noalloc call keeps its tables inside the scratch
+// (byte offsets from its start) and the work-item plan of its instance.
+struct NoallocLayout {
+    uint64_t off_win, off_inst, off_state, off_ctr, off_bad, off_jobs, off_work, off_gq, bytes;
+    uint64_t size, small;       // candidates per head item / per tail item
+    uint32_t n_head, n_items;   // head items; all items
+    int32_t n, t, l, d, stride, layout;
+};
+
+// The scratch's device address and size (hipGetSymbolAddress; call with the
+// device current).
+hipError_t noalloc_scratch(void** ptr, size_t* bytes);
+// Builds the call's records in the scratch (no host copy).
+hipError_t launch_noalloc_setup(void* base, const NoallocLayout& lay, uint32_t* dev_out,
+                                uint64_t capacity, hipStream_t stream);
+// Copies the instance's motif count to *dev_count.
+hipError_t launch_noalloc_count(const pms_dev_state* st, uint64_t* dev_count, hipStream_t stream);
+
 // Where a grouped launch keeps its stage queues: the first lds_stages in LDS,
 // the rest in gq (gq_words words per wavefront, grid x wg_waves wavefronts).
 struct GroupQueues {

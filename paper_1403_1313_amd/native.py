@@ -21,7 +21,7 @@ PMS_MAX_L, PMS_MAX_N, PMS_MAX_T = 16, 64, 1 << 17
 SYMBOLS = ["pms_solve", "pms_solve_ex", "pms_solve_intersect", "pms_solve_many", "pms_decode", "pms_status_string", "pms_last_error",
            "pms_set_config", "pms_get_config", "pms_autotune", "pms_last_stats",
            "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev",
-           "pms_valu_probe"]
+           "pms_valu_probe", "pms_solve_dev_noalloc"]
 PROBE_OPS = {"xor": 0, "bcnt": 1, "min3": 2, "or_sdwa": 3, "add": 4, "fma_f32": 5, "xor_vv": 6,
              "compare": 7, "mov_s": 8, "mov64_s": 9}
 
@@ -152,6 +152,7 @@ def _load():
         "pms_step_launch": ([vp, i32, i32, vp, i32, vp, vp, P(Config), vp], ctypes.c_int),
         "pms_solve_dev": ([vp, i32, i32, i32, i32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
         "pms_valu_probe": ([ctypes.c_int, i32, i32, P(ProbeResult)], ctypes.c_int),
+        "pms_solve_dev_noalloc": ([vp, i32, i32, i32, i32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -393,6 +394,14 @@ def build_windows(dev_seqs, n: int, t: int, l: int, dev_windows, dev_bad=None, s
 def solve_dev(dev_seqs, n: int, t: int, l: int, d: int, dev_out, capacity: int, dev_count,
               stream=None):
     return _check(_lib.pms_solve_dev(
+        dev_seqs.data_ptr(), n, t, l, d, dev_out.data_ptr() if capacity else None, capacity,
+        dev_count.data_ptr(), _stream_handle(stream)))
+
+
+def solve_dev_noalloc(dev_seqs, n: int, t: int, l: int, d: int, dev_out, capacity: int,
+                      dev_count, stream=None):
+    """pms_solve_dev_noalloc: pms_solve_dev with the library's fixed scratch."""
+    return _check(_lib.pms_solve_dev_noalloc(
         dev_seqs.data_ptr(), n, t, l, d, dev_out.data_ptr() if capacity else None, capacity,
         dev_count.data_ptr(), _stream_handle(stream)))
 

@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 16
+    assert len(names) == 17
     assert sorted(nat.SYMBOLS) == names
     lib = ctypes.CDLL(nat.LIB_PATH)
     for name in names:
@@ -264,3 +264,19 @@ def test_probe_rejects_unknown_kinds():
     r = nat.ProbeResult()
     for bad in (-1, max(kinds.values()) + 1):
         assert nat._lib.pms_valu_probe(bad, 0, 0, ctypes.byref(r)) == nat.PMS_ERR_INVALID
+
+
+def test_solve_dev_noalloc_rejects_bad_arguments():
+    """pms_solve_dev_noalloc checks pointers and sizes before any device work;
+    the scratch limit is published in the header."""
+    lib = nat.lib()
+    cnt = ctypes.c_uint64(0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below is refused first
+    assert lib.pms_solve_dev_noalloc(None, 2, 8, 4, 1, fake, 8, fake, None) == nat.PMS_ERR_INVALID
+    assert lib.pms_solve_dev_noalloc(fake, 2, 8, 4, 1, None, 8, fake, None) == nat.PMS_ERR_INVALID
+    assert lib.pms_solve_dev_noalloc(fake, 2, 8, 4, 1, fake, 8, None, None) == nat.PMS_ERR_INVALID
+    for n, t, l, d in [(0, 8, 4, 1), (65, 8, 4, 1), (2, 3, 4, 1), (2, 8, 17, 1), (2, 8, 4, 5)]:
+        assert lib.pms_solve_dev_noalloc(fake, n, t, l, d, fake, 8, fake, None) == nat.PMS_ERR_INVALID
+    text = open(HEADER).read()
+    assert re.search(r"#define PMS_NOALLOC_SCRATCH_BYTES \(128u << 20\)", text)
+    del cnt
