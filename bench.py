@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--variant", default="auto", choices=["auto", "lane", "group16", "group64"],
                     help="search kernel variant")
+    ap.add_argument("--filter", default="on", choices=["on", "off"],
+                    help="window filter of the 64-candidate kernel (off: every window scanned)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -147,7 +149,8 @@ def bench_plain(args):
     import fmgen
     from paper_1403_1313_amd import native as nat
 
-    nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant])
+    nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant],
+                   filter=nat.FILTER_ON if args.filter == "on" else nat.FILTER_OFF)
     shape = fmgen.PLAIN[args.config]
     inst = fmgen.gen_fm(seed=args.seed, **shape)
     l, d, n, t = inst.l, inst.d, inst.n, inst.t
@@ -257,6 +260,9 @@ def bench_plain(args):
         "candidate_slots": st["candidate_slots"],
         "batches": st["batches"],
         "single_batches": st["single_batches"],
+        "filter": args.filter,
+        "filtered_batches": st["filtered_batches"],
+        "filtered_dense_groups": st["filtered_groups"],
         "slot_efficiency": st["seq_visits"] / max(1, st["candidate_slots"]),
         "variant": nat.VARIANT_NAMES[st["variant"]],
         "motifs": int(codes.size),

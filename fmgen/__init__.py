@@ -148,3 +148,13 @@ def serving_stream(count: int, rate: float, master_seed: int = 1313):
         seed = int(rng.integers(2 ** 63))
         out.append((t_now, Spec(l, d, n, t, seed)))
     return out
+
+
+def serving_check_specs() -> List[Spec]:
+    """Requests of the serving workload with stored oracle results: the first
+    13 requests of ``serving_stream(64, 100.0)`` ((9,2), (11,3) and four
+    (13,4)), its two (15,4) requests at positions 19 and 31, and one (13,4)
+    request at n = 10, t = 1000, the largest output the workload draws
+    (about 6e5 motifs; seed 1313)."""
+    stream = [spec for _, spec in serving_stream(64, 100.0)]
+    return stream[:13] + [stream[19], stream[31], Spec(13, 4, 10, 1000, 1313)]

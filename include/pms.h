@@ -179,6 +179,19 @@ enum pms_input_flag {
     PMS_INPUT_BOTH_STRANDS = 2
 };
 
+/* Window filter of the 64-candidate kernel (pms_config.filter).  When the
+ * live groups of a sequence scan all share their first l-6 bases, a window
+ * whose mismatches on those bases already exceed d cannot match any of their
+ * candidates; the filter scans only the other windows (re-sliced into dense
+ * 32-window groups).  Exact: the same motifs, the same sequence visits.  An
+ * extension of the enhanced rule of Section III.A, not part of the paper's
+ * method; OFF gives the unfiltered scan for comparison. */
+enum pms_filter {
+    PMS_FILTER_DEFAULT = 0, /* ON */
+    PMS_FILTER_ON = 1,
+    PMS_FILTER_OFF = 2
+};
+
 /* Shape of the persistent search launch.  Zero fields mean "default". */
 typedef struct {
     uint32_t chunk;        /* least candidates per work item (multiple of 64); items are
@@ -189,6 +202,7 @@ typedef struct {
                               cut 4x smaller, so the launch ends evenly (0..64; the
                               default, 0, splits nothing) */
     uint32_t variant;      /* pms_variant */
+    uint32_t filter;       /* pms_filter: window filter of the 64-candidate kernel */
 } pms_config;
 
 /* Sets the configuration used by later calls that pass no configuration
@@ -233,6 +247,10 @@ typedef struct {
     double host_finish_ms;   /* host-level calls: copy-back, sort and capacity handling
                                 after the launch, reruns included (0 for device-level) */
     uint64_t single_batches; /* of `batches`: GROUP64 scans of one candidate per lane */
+    uint64_t filtered_batches; /* of `batches`: group scans through the window filter
+                                  (pms_filter); the rest of those batches' windows
+                                  were skipped */
+    uint64_t filtered_groups;  /* dense 32-window groups the filtered scans ran */
 } pms_stats;
 
 int pms_last_stats(pms_stats* out);
@@ -336,6 +354,8 @@ typedef struct {
     uint64_t batches;    /* 64-lane sequence scans executed */
     uint64_t t_start;    /* realtime stamp of the first claim */
     uint64_t single_batches; /* of those, scans of one candidate per lane (GROUP64) */
+    uint64_t filtered_batches; /* of those, group scans through the window filter */
+    uint64_t filtered_groups;  /* dense 32-window groups those scans ran */
 } pms_dev_counters;
 
 /*
@@ -368,6 +388,21 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
  */
 int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
                   uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count, void* stream);
+
+/*
+ * pms_shutdown -- releases every device and pinned-host resource the library
+ * holds for the device (stream, events, the captured graph, workspaces,
+ * staging buffers; the fixed scratch of pms_solve_dev_noalloc is a static
+ * array and stays), after waiting for all work on the device, including
+ * device-level calls still running on callers' streams.  A later call
+ * creates them again.  Meant for the end of a process (the Python binding
+ * registers it to run at interpreter exit), so that no library-owned HIP
+ * object outlives the HIP runtime's own teardown; no other thread may be
+ * inside the library meanwhile.  PMS_OK, or PMS_ERR_DEVICE with the first
+ * failing release named in pms_last_error() (the rest are still released).
+ * Makes no HIP call when the library never touched a device.
+ */
+int pms_shutdown(void);
 
 /*
  * pms_solve_dev_noalloc -- pms_solve_dev for callers that cannot allocate

@@ -32,9 +32,20 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found; install ROCm or set HIPCC")
 
 
+def build_id() -> str:
+    """Hash of the library's sources and headers (keys the autotune cache)."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in sorted(SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+                       + [os.path.join(INCLUDE, "pms.h")]):
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + b"\0" + f.read())
+    return h.hexdigest()[:12]
+
+
 def build(out: str = LIB, extra=(), verbose: bool = False) -> str:
     tmp = out + ".tmp"
-    cmd = [hipcc(), *FLAGS, *extra, *SOURCES, "-o", tmp]
+    cmd = [hipcc(), *FLAGS, f'-DPMS_BUILD_ID="{build_id()}"', *extra, *SOURCES, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)

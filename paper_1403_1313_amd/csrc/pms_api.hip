@@ -53,11 +53,15 @@ int fail(int status, const std::string& msg) {
     } while (0)
 
 // Forced failure for tests of error propagation: PMS_TEST_FAIL_NEXT=<status>
-// makes the next host-level call return that status (the variable is then
-// cleared).  Checked before any device work.
-int test_hook() {
+// makes the next call of an entry point that does device work return that
+// status (the variable is then cleared); <status>:<entry point name> aims it
+// at the next call of that entry point only (others leave it set).  Checked
+// after argument validation, before any device work.
+int test_hook(const char* entry) {
     const char* v = getenv("PMS_TEST_FAIL_NEXT");
     if (!v || !*v) return PMS_OK;
+    const char* colon = strchr(v, ':');
+    if (colon && strcmp(colon + 1, entry) != 0) return PMS_OK;
     const int s = atoi(v);
     unsetenv("PMS_TEST_FAIL_NEXT");
     if (s <= PMS_OK || s > PMS_ERR_DEVICE) return PMS_OK;
@@ -85,6 +89,12 @@ struct DevBuf {
         cap = want;
         return PMS_OK;
     }
+    hipError_t release() {
+        const hipError_t e = p ? hipFree(p) : hipSuccess;
+        p = nullptr;
+        cap = 0;
+        return e;
+    }
     template <typename T>
     T* as(size_t byte_off = 0) const { return reinterpret_cast<T*>(static_cast<char*>(p) + byte_off); }
 };
@@ -104,6 +114,12 @@ struct HostBuf {
         cap = want;
         return PMS_OK;
     }
+    hipError_t release() {
+        const hipError_t e = p ? hipHostFree(p) : hipSuccess;
+        p = nullptr;
+        cap = 0;
+        return e;
+    }
     template <typename T>
     T* as(size_t byte_off = 0) const { return reinterpret_cast<T*>(static_cast<char*>(p) + byte_off); }
 };
@@ -118,13 +134,14 @@ pms_config default_config() {
     c.wgs_per_cu = 0;
     c.tail_split = 0;
     c.variant = PMS_VARIANT_AUTO;
+    c.filter = PMS_FILTER_DEFAULT;
     return c;
 }
 
 bool config_ok(const pms_config& c) {
     return c.chunk >= 64 && c.chunk % 64 == 0 && c.chunk <= (1u << 24) && c.wg_waves >= 1 &&
            c.wg_waves <= 16 && c.wgs_per_cu <= 64 && c.tail_split <= 64 &&
-           c.variant <= PMS_VARIANT_GROUP64;
+           c.variant <= PMS_VARIANT_GROUP64 && c.filter <= PMS_FILTER_OFF;
 }
 
 pms_config resolve(const pms_config* c, const pms_config& cur) {
@@ -278,6 +295,7 @@ struct Batch {
     size_t raw_bytes = 0, win_words = 0, out_words = 0;
     int32_t max_n = 1, max_t = 1;
     uint32_t variant = PMS_VARIANT_LANE;  // kernel variant chosen for this launch
+    uint32_t flags = 0;                   // PMS_LAUNCH_* flags of the search launch
     // meta layout (bytes) inside d_meta / h_meta
     size_t off_insts = 0, off_jobs = 0, off_work = 0, off_state = 0, off_ctr = 0, off_bad = 0,
            meta_bytes = 0;
@@ -525,6 +543,11 @@ uint32_t choose_variant(const std::vector<Shape>& shapes, uint32_t requested) {
     return v;
 }
 
+// Search-launch flags of a configuration.
+uint32_t launch_flags(const pms_config& cfg) {
+    return cfg.filter == PMS_FILTER_OFF ? PMS_LAUNCH_NO_FILTER : 0u;
+}
+
 // Lays out raw bytes, windows, outputs and the meta block for the instances.
 // target_items: about how many work items the launch should have in all.
 void plan_batch(Batch& b, const pms_config& cfg, uint64_t target_items) {
@@ -538,6 +561,7 @@ void plan_batch(Batch& b, const pms_config& cfg, uint64_t target_items) {
     b.max_n = 1;
     b.max_t = 1;
     b.variant = choose_variant(b.shape, cfg.variant);
+    b.flags = launch_flags(cfg);
     const int32_t layout = b.variant == PMS_VARIANT_LANE ? PMS_LAYOUT_PLANES : PMS_LAYOUT_BITSLICED;
     std::vector<double> cost(m);
     for (size_t i = 0; i < m; ++i) {
@@ -624,13 +648,13 @@ int stage_batch(Ctx& c, Batch& b) {
     return PMS_OK;
 }
 
-hipError_t launch_variant(uint32_t variant, const pms_dev_instance* insts,
+hipError_t launch_variant(uint32_t variant, uint32_t flags, const pms_dev_instance* insts,
                           const pms_work_item* work, uint32_t n_work, pms_dev_state* state,
                           pms_dev_counters* ctr, const Shape2& sh, hipStream_t s) {
     if (variant == PMS_VARIANT_LANE)
         return pms::launch_search(insts, work, n_work, state, ctr, sh.q_words, sh.grid, sh.waves, s);
     return pms::launch_search_group(insts, work, n_work, state, ctr, sh.gq, sh.grid, sh.waves, s,
-                                    variant == PMS_VARIANT_GROUP64 ? 3 : 2);
+                                    variant == PMS_VARIANT_GROUP64 ? 3 : 2, flags);
 }
 
 // Enqueues copy-in, both kernels and copy-back of the state block on c.stream.
@@ -644,7 +668,7 @@ int enqueue_batch(Ctx& c, const Batch& b, bool timed, const Shape2& sh) {
                                 c.d_raw.as<uint8_t>(), c.d_win.as<uint32_t>(),
                                 reinterpret_cast<uint32_t*>(dm + b.off_bad), c.stream));
     if (timed) PMS_HIP(hipEventRecord(c.ev[1], c.stream));
-    PMS_HIP(launch_variant(b.variant, reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
+    PMS_HIP(launch_variant(b.variant, b.flags, reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
                            reinterpret_cast<const pms_work_item*>(dm + b.off_work),
                            static_cast<uint32_t>(b.work.size()),
                            reinterpret_cast<pms_dev_state*>(dm + b.off_state),
@@ -662,7 +686,7 @@ std::string graph_signature(const Ctx& c, const Batch& b, const pms_config& cfg)
       << b.meta_bytes << ':' << b.off_state << ':' << b.jobs.size() << ':' << b.work.size()
       << ':' << b.max_n << ':' << b.max_t << ':' << cfg.chunk << ':' << cfg.wg_waves << ':'
       << cfg.wgs_per_cu << ':' << b.shape.size() << ':' << b.off_insts << ':' << b.off_jobs << ':'
-      << b.off_work << ':' << b.off_ctr << ':' << b.off_bad << ':' << b.variant;
+      << b.off_work << ':' << b.off_ctr << ':' << b.off_bad << ':' << b.variant << ':' << b.flags;
     return o.str();
 }
 
@@ -804,6 +828,8 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     c.last.window_compares = wcmp;
     c.last.batches = ctr->batches;
     c.last.single_batches = ctr->single_batches;
+    c.last.filtered_batches = ctr->filtered_batches;
+    c.last.filtered_groups = ctr->filtered_groups;
     c.last.candidate_slots = candidate_slots(*ctr, b.variant);
     c.last.reruns = 0;
     // Step a7.  Every instance's codes go to its segment of one pinned
@@ -904,15 +930,22 @@ std::vector<std::string> synthetic_rows(int32_t n, int32_t t, int32_t l, int32_t
     return rows;
 }
 
+// Cache key of a tuned configuration: the build (a hash of the library's
+// sources, so that a setting tuned on other kernels is never reused), the
+// device, the requested variant and filter, and the shape bucket.
+#ifndef PMS_BUILD_ID
+#define PMS_BUILD_ID "unversioned"
+#endif
 std::string tune_key(const Ctx& c, int32_t n, int32_t t, int32_t l, int32_t d) {
     std::ostringstream o;
-    o << c.arch << "/cu" << c.cus << "/v" << c.cfg.variant << "/l" << l << "/d" << d << "/n" << n
-      << "/nw" << align_up(static_cast<size_t>(t - l + 1), 128);
+    o << PMS_BUILD_ID << "/" << c.arch << "/cu" << c.cus << "/v" << c.cfg.variant << "/f"
+      << c.cfg.filter << "/l" << l << "/d" << d << "/n" << n << "/nw"
+      << align_up(static_cast<size_t>(t - l + 1), 128);
     return o.str();
 }
 
 // The cache file is one flat JSON object:
-// {"key": [chunk, wg_waves, wgs_per_cu, tail_split, variant], ...}
+// {"key": [chunk, wg_waves, wgs_per_cu, tail_split, variant, filter], ...}
 bool cache_lookup(const std::string& path, const std::string& key, pms_config* out) {
     std::ifstream f(path);
     if (!f) return false;
@@ -922,10 +955,10 @@ bool cache_lookup(const std::string& path, const std::string& key, pms_config* o
     const std::string pat = "\"" + key + "\": [";
     const size_t p = s.find(pat);
     if (p == std::string::npos) return false;
-    unsigned a = 0, b = 0, cc = 0, dd = 0, ee = 0;
-    if (sscanf(s.c_str() + p + pat.size(), "%u, %u, %u, %u, %u", &a, &b, &cc, &dd, &ee) != 5)
+    unsigned a = 0, b = 0, cc = 0, dd = 0, ee = 0, ff = 0;
+    if (sscanf(s.c_str() + p + pat.size(), "%u, %u, %u, %u, %u, %u", &a, &b, &cc, &dd, &ee, &ff) != 6)
         return false;
-    pms_config r{a, b, cc, dd, ee};
+    pms_config r{a, b, cc, dd, ee, ff};
     if (!config_ok(r)) return false;
     *out = r;
     return true;
@@ -948,7 +981,7 @@ void cache_store(const std::string& path, const std::string& key, const pms_conf
     }
     std::ostringstream v;
     v << cfg.chunk << ", " << cfg.wg_waves << ", " << cfg.wgs_per_cu << ", " << cfg.tail_split << ", "
-      << cfg.variant;
+      << cfg.variant << ", " << cfg.filter;
     entries.emplace_back(key, v.str());
     std::ofstream f(path + ".tmp");
     f << "{\n";
@@ -1021,7 +1054,7 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t 
     PMS_TRY(validate_shape(n, t, l, d));
     if (cap > 0 && !out_motifs) return fail(PMS_ERR_INVALID, "out_motifs is NULL with capacity > 0");
     PMS_TRY(validate_rows(seqs, n, t));
-    PMS_TRY(test_hook());
+    PMS_TRY(test_hook("pms_solve"));
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     PMS_TRY(init_ctx(g_ctx));
     g_ctx.t_call = t_call;
@@ -1056,7 +1089,7 @@ int pms_solve_ex(const char* const* seqs, int32_t n, const int32_t* lengths, int
     if (cap > 0 && !out_motifs) return fail(PMS_ERR_INVALID, "out_motifs is NULL with capacity > 0");
     bool empty = false;
     PMS_TRY(validate_rows_ex(seqs, n, lengths, l, flags, &empty));
-    PMS_TRY(test_hook());
+    PMS_TRY(test_hook("pms_solve_ex"));
     if (empty) return PMS_OK;  // a sequence without windows: no l-mer matches all
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     PMS_TRY(init_ctx(g_ctx));
@@ -1115,7 +1148,7 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
     if (ball_size(l, d) > PMS_NBHD_MAX_BALL)
         return fail(PMS_ERR_INVALID, "distance-d ball larger than PMS_NBHD_MAX_BALL masks");
     PMS_TRY(validate_rows(seqs, n, t));
-    PMS_TRY(test_hook());
+    PMS_TRY(test_hook("pms_solve_intersect"));
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     Ctx& c = g_ctx;
     PMS_TRY(init_ctx(c));
@@ -1347,7 +1380,7 @@ int pms_solve_many(const pms_instance* inst, int32_t count, pms_result* results)
         if (first_bad != PMS_OK) g_last_error = first_msg;
         return first_bad;
     }
-    PMS_TRY(test_hook());
+    PMS_TRY(test_hook("pms_solve_many"));
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     PMS_TRY(init_ctx(g_ctx));
     g_ctx.t_call = t_call;
@@ -1388,6 +1421,8 @@ int pms_last_stats(pms_stats* out) {
             c.last.window_compares = st.visits * static_cast<uint64_t>(c.dv_nw);
             c.last.batches = ctr.batches;
             c.last.single_batches = ctr.single_batches;
+            c.last.filtered_batches = ctr.filtered_batches;
+            c.last.filtered_groups = ctr.filtered_groups;
             c.last.candidate_slots = candidate_slots(ctr, c.dv_variant);
         }
         c.last_pending = false;
@@ -1404,6 +1439,7 @@ int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, 
         return fail(PMS_ERR_INVALID, "size out of range");
     if (layout != PMS_LAYOUT_PLANES && (layout != PMS_LAYOUT_BITSLICED || l < 2))
         return fail(PMS_ERR_INVALID, "bad layout (BITSLICED needs l >= 2)");
+    PMS_TRY(test_hook("pms_build_windows"));
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     Ctx& c = g_ctx;
     PMS_TRY(init_ctx(c));
@@ -1439,6 +1475,7 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
         return fail(PMS_ERR_INVALID, "NULL device pointer");
     if (n_inst < 1 || n_work < 0 || max_n < 1 || max_n > PMS_MAX_N)
         return fail(PMS_ERR_INVALID, "table size out of range");
+    PMS_TRY(test_hook("pms_step_launch"));
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     Ctx& c = g_ctx;
     PMS_TRY(init_ctx(c));
@@ -1451,7 +1488,7 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
     hipStream_t s = static_cast<hipStream_t>(stream);
     PMS_HIP(hipEventRecord(c.ev[0], s));
     PMS_HIP(hipEventRecord(c.ev[1], s));
-    PMS_HIP(launch_variant(variant, dev_instances, dev_work, static_cast<uint32_t>(n_work), dev_state,
+    PMS_HIP(launch_variant(variant, launch_flags(r), dev_instances, dev_work, static_cast<uint32_t>(n_work), dev_state,
                            dev_counters, sh, s));
     PMS_HIP(hipEventRecord(c.ev[2], s));
     c.last = pms_stats{};
@@ -1470,6 +1507,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     if (!dev_seqs || !dev_count || (capacity > 0 && !dev_out))
         return fail(PMS_ERR_INVALID, "NULL device pointer");
     PMS_TRY(validate_shape(n, t, l, d));
+    PMS_TRY(test_hook("pms_solve_dev"));
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     Ctx& c = g_ctx;
     PMS_TRY(init_ctx(c));
@@ -1477,7 +1515,8 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     const pms_config cfg = c.cfg;
     std::ostringstream kss;
     kss << n << ':' << t << ':' << l << ':' << d << ':' << cfg.chunk << ':' << cfg.wg_waves << ':'
-        << cfg.wgs_per_cu << ':' << cfg.tail_split << ':' << cfg.variant << ':' << target_items(c);
+        << cfg.wgs_per_cu << ':' << cfg.tail_split << ':' << cfg.variant << ':' << cfg.filter << ':'
+        << target_items(c);
     const std::string key = kss.str();
     const bool reuse = c.dv_plan_valid && key == c.dv_key;
     if (!reuse) {
@@ -1528,7 +1567,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
                                 dev_seqs, c.dv_win.as<uint32_t>(),
                                 reinterpret_cast<uint32_t*>(dm + b.off_bad), s));
     PMS_HIP(hipEventRecord(c.ev[1], s));
-    PMS_HIP(launch_variant(b.variant, reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
+    PMS_HIP(launch_variant(b.variant, b.flags, reinterpret_cast<const pms_dev_instance*>(dm + b.off_insts),
                            reinterpret_cast<const pms_work_item*>(dm + b.off_work),
                            static_cast<uint32_t>(b.work.size()),
                            reinterpret_cast<pms_dev_state*>(dm + b.off_state),
@@ -1555,6 +1594,61 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     return PMS_OK;
 }
 
+int pms_shutdown(void) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    if (!c.dev_ready) return PMS_OK;  // nothing was created
+    int status = PMS_OK;
+    auto note = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && status == PMS_OK)
+            status = fail(PMS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    note(hipSetDevice(c.device), "hipSetDevice");
+    // Device-level calls may still run on callers' streams with library
+    // buffers: everything on the device completes first.
+    note(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (c.gexec) note(hipGraphExecDestroy(c.gexec), "hipGraphExecDestroy");
+    c.gexec = nullptr;
+    c.gsig.clear();
+    for (auto& e : c.ev) {
+        if (e) note(hipEventDestroy(e), "hipEventDestroy");
+        e = nullptr;
+    }
+    for (hipEvent_t* e : {&c.dv_copied, &c.dv_back}) {
+        if (*e) note(hipEventDestroy(*e), "hipEventDestroy");
+        *e = nullptr;
+    }
+    for (int i = 0; i < Ctx::kJobRing; ++i) {
+        if (c.bw_ev[i]) note(hipEventDestroy(c.bw_ev[i]), "hipEventDestroy");
+        c.bw_ev[i] = nullptr;
+        c.bw_live[i] = false;
+    }
+    c.bw_next = 0;
+    if (c.stream) note(hipStreamDestroy(c.stream), "hipStreamDestroy");
+    c.stream = nullptr;
+    for (DevBuf* b : {&c.d_raw, &c.d_win, &c.d_out, &c.d_meta, &c.d_gq, &c.dv_win, &c.dv_meta,
+                      &c.dv_gq, &c.bw_dev, &c.nb_m, &c.nb_b, &c.nb_codes, &c.nb_deltas,
+                      &c.nb_groups, &c.nb_ne, &c.nb_cand, &c.nb_out, &c.nb_count, &c.nb_tcount,
+                      &c.nb_toff, &c.nb_tcur, &c.nb_rec, &c.nb_part})
+        note(b->release(), "hipFree");
+    for (HostBuf* b : {&c.h_raw, &c.h_meta, &c.h_back, &c.h_out, &c.hv_meta, &c.hv_back, &c.bw_host})
+        note(b->release(), "hipHostFree");
+    c.nb_ball_l = c.nb_ball_d = -1;
+    c.nb_ball_size = c.nb_nne = 0;
+    c.dv_plan_valid = false;
+    c.dv_uploaded = nullptr;
+    c.dv_copy_live = false;
+    c.dv_counters = false;
+    c.last_pending = false;
+    c.shapes.clear();
+    c.ready = false;
+    c.dev_ready = false;
+    c.scratch = nullptr;
+    c.scratch_bytes = 0;
+    return status;
+}
+
 int pms_solve_dev_noalloc(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
                           uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count,
                           void* stream) {
@@ -1562,6 +1656,7 @@ int pms_solve_dev_noalloc(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t
     if (!dev_seqs || !dev_count || (capacity > 0 && !dev_out))
         return fail(PMS_ERR_INVALID, "NULL device pointer");
     PMS_TRY(validate_shape(n, t, l, d));
+    PMS_TRY(test_hook("pms_solve_dev_noalloc"));
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     Ctx& c = g_ctx;
     PMS_TRY(init_device(c));
@@ -1631,7 +1726,8 @@ int pms_solve_dev_noalloc(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t
     PMS_HIP(pms::launch_windows(reinterpret_cast<const pms_win_job*>(base + lay.off_jobs), n, t,
                                 dev_seqs, reinterpret_cast<uint32_t*>(base + lay.off_win),
                                 reinterpret_cast<uint32_t*>(base + lay.off_bad), s));
-    PMS_HIP(launch_variant(variant, reinterpret_cast<const pms_dev_instance*>(base + lay.off_inst),
+    PMS_HIP(launch_variant(variant, launch_flags(cfg),
+                           reinterpret_cast<const pms_dev_instance*>(base + lay.off_inst),
                            reinterpret_cast<const pms_work_item*>(base + lay.off_work),
                            lay.n_items, reinterpret_cast<pms_dev_state*>(base + lay.off_state),
                            reinterpret_cast<pms_dev_counters*>(base + lay.off_ctr), sh, s));
@@ -1676,9 +1772,12 @@ int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_p
     const uint32_t tails[] = {0, 8};
     for (uint32_t ch : chunks) {
         if (ch > total && ch != chunks[0]) continue;
+        // From l = 6 on items are whole multiples of 4096 candidates, so a
+        // smaller chunk gives the same plan as 4096.
+        if (ch < 4096 && total >= 4096) continue;
         for (uint32_t w : waves) {
             for (uint32_t tail : tails) {
-                pms_config cfg{ch, w, 0, tail, c.cfg.variant};
+                pms_config cfg{ch, w, 0, tail, c.cfg.variant, c.cfg.filter};
                 Batch b;
                 b.shape = {Shape{n, t, l, d}};
                 b.rows = {ptrs.data()};

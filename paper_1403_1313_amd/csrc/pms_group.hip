@@ -55,6 +55,7 @@ constexpr uint32_t kOr3 = 0xFE;      // a | b | c
 constexpr uint32_t kAnd3 = 0x80;     // a & b & c
 constexpr uint32_t kNandOr = 0x1F;   // ~(a & (b | c))
 constexpr uint32_t kNorAnd = 0x07;   // ~(a | (b & c))
+constexpr uint32_t kOrXor = 0xF6;    // a | (b ^ c)
 
 // Bit-sliced sum of P one-bit vectors plus a wave-uniform bias B < 32 given
 // as five all-ones / all-zero masks bias[i] = bit i of B:
@@ -95,6 +96,13 @@ __device__ __forceinline__ void count_bits(const uint32_t (&m)[P > 0 ? P : 1],
 #pragma unroll
     for (int k = 0; k < 5; ++k) c[k] = nw[k] ? w[k][0] : 0u;
 }
+
+// v_writelane_b32: lane `lane` of `old` replaced by the wave-uniform `val`
+// (the LLVM intrinsic, which clang exposes under no builtin name here).  Not
+// written as inline asm: v_writelane reads its SGPR operand early, so it
+// needs wait states after the VALU instruction that wrote it (a ballot's
+// v_cmp), which the compiler inserts for the intrinsic but not around asm.
+__device__ int write_lane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
 // A wave-uniform value copied into a VGPR.  VALU instructions that read an
 // SGPR issue at half rate on gfx950; the selection tree below reads these
@@ -473,6 +481,226 @@ __device__ __forceinline__ uint64_t scan_group_shared_any(uint32_t P, cu32* W, u
     }
 }
 
+// Window filter for 64 groups that all lie in one block of 64 consecutive
+// groups (they share their first Q = P - 3 bases, the block number kv).  A
+// window whose mismatch count over the shared bases exceeds d is farther than
+// d from every candidate of the block, so only the windows with
+// U_0 = [shared count <= d] set can matter; the others cannot change any
+// candidate's result (an exact filter on top of the enhanced rule, which it
+// leaves unchanged: the same candidates reach the same sequences).
+//
+// filter_windows builds the block's thresholds (table lane j < groups: U_0..
+// U_6 of window group j, as in scan_group_shared, and the window group's
+// plane words of the six unshared positions: 3 lane, 3 suffix, high then low
+// plane), then re-slices the windows with U_0 set into dense 32-window
+// groups in the wavefront's LDS table `svt`, 20 words each:
+//   U_0..U_6, high plane of the six positions, low plane of the six.
+//  * Windows are taken 64 at a time (two window groups, one per lane); the
+//    survivors move to consecutive lanes with one ds_permute (a rotation of
+//    the stable compaction order, so that no two lanes collide) and gather
+//    until 64 are pending.
+//  * 64 pending windows (or the rest, at the end) are re-sliced: each lane
+//    fetches its window's 19 words from the table lane (ds_bpermute) and one
+//    ballot per word forms the new bit-sliced words.  Lanes past the pending
+//    count give all-zero words: U_0 = 0 there, which no candidate passes.
+// Returns the number of dense groups, or kNoFit when they would not fit in
+// the table (the caller then scans every window).  No per-candidate state
+// is live here, which keeps the register budget of scan_filtered's loop.
+// Requires 3 <= P <= 13 and groups <= 64.
+constexpr uint32_t kNoFit = 0xffffffffu;
+constexpr uint32_t kDenseWords = 20u;
+constexpr uint32_t kDenseMax = PMS_SVT_WORDS / kDenseWords;
+
+template <int P>
+__device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uint32_t kv, int d,
+                                                   uint32_t* __restrict__ svt) {
+    constexpr int L = P + 3;
+    constexpr int Q = P - 3;
+    uint32_t ln = lane_id();
+    asm volatile("" : "+v"(ln));
+    uint32_t u[7], pw[12];
+    {
+        const uint32_t bias_value = static_cast<uint32_t>(19 - d);
+        uint32_t bias[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) bias[i] = 0u - ((bias_value >> i) & 1u);
+        uint32_t m[Q > 0 ? Q : 1];
+#pragma unroll
+        for (int p = 0; p < (Q > 0 ? Q : 1); ++p) m[p] = 0u;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) pw[i] = 0u;
+        const bool table = ln < groups;
+        if (table) {
+            const uint32_t* row = (const uint32_t*)(W) + ln * (2u * L);
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const uint32_t b = (kv >> (2 * (Q - 1 - p))) & 3u;
+                m[p] = (row[p] ^ (0u - (b >> 1))) | (row[L + p] ^ (0u - (b & 1u)));
+            }
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                pw[i] = row[Q + i];
+                pw[6 + i] = row[L + Q + i];
+            }
+        }
+        uint32_t c[5];
+        count_bits<Q>(m, bias, c);
+        // Lanes past the last window group hold no windows.
+        const uint32_t on = table ? ~0u : 0u;
+        u[0] = on & ~(c[4] & (c[3] | c[2]));
+        u[1] = on & ~(c[4] & (c[3] | c[2] | (c[1] & c[0])));
+        u[2] = on & ~(c[4] & (c[3] | c[2] | c[1]));
+        u[3] = on & ~(c[4] & (c[3] | c[2] | c[1] | c[0]));
+        u[4] = on & ~c[4];
+        u[5] = on & ~(c[4] | (c[3] & c[2] & c[1] & c[0]));
+        u[6] = on & ~(c[4] | (c[3] & c[2] & c[1]));
+    }
+    // Windows to keep: the sum over lanes of popcount(U_0), bit by bit.
+    const uint32_t pc = static_cast<uint32_t>(__builtin_popcount(u[0]));
+    uint32_t total = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        total += static_cast<uint32_t>(__builtin_popcountll(ballot((pc >> b) & 1u))) << b;
+    const uint32_t dense = (total + 31u) >> 5;
+    if (dense > kDenseMax) return kNoFit;
+    const uint32_t slabs = (groups + 1u) >> 1;
+    uint32_t sb = 0, r = 0, nv = 0;   // next slab; windows pending; dense groups written
+    uint32_t pend = 0;                // lanes < r: a pending window number
+    for (;;) {
+        uint32_t fidx, fcnt;
+        if (sb < slabs) {
+            // Slab sb: windows 64 sb + lane, of window groups 2 sb and 2 sb + 1.
+            const uint32_t j = 2u * sb + (ln >> 5);
+            const uint32_t m0 = static_cast<uint32_t>(
+                __builtin_amdgcn_ds_bpermute(static_cast<int>(j << 2), static_cast<int>(u[0])));
+            const bool hit = ((m0 >> (ln & 31u)) & 1u) != 0u;
+            const uint64_t hm = ballot(hit);
+            const uint32_t w = 64u * sb + ln;
+            ++sb;
+            if (hm == 0) continue;
+            const uint32_t cnt = static_cast<uint32_t>(__builtin_popcountll(hm));
+            const uint32_t rk = hit ? rank_below(hm) : cnt + rank_below(~hm);
+            const uint32_t got = static_cast<uint32_t>(__builtin_amdgcn_ds_permute(
+                static_cast<int>(((r + rk) & 63u) << 2), static_cast<int>(w)));
+            if (r + cnt < 64u) {
+                if (((ln - r) & 63u) < cnt) pend = got;
+                r += cnt;
+                continue;
+            }
+            fidx = ln >= r ? got : pend;
+            fcnt = 64u;
+            r = r + cnt - 64u;
+            pend = got;
+        } else {
+            if (r == 0) break;
+            fidx = pend;
+            fcnt = r;
+            r = 0;
+        }
+        // Re-slice the fcnt windows held by lanes 0 .. fcnt-1: word i of the
+        // dense group(s) is ballot i, written by lane i.
+        const bool valid = ln < fcnt;
+        const uint32_t wi = valid ? fidx : 0u;
+        const int src = static_cast<int>((wi >> 5) << 2);
+        const uint32_t bit = wi & 31u;
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const uint32_t x = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(
+                src, static_cast<int>(i < 7 ? u[i] : pw[i - 7])));
+            const uint64_t bm = ballot(valid && ((x >> bit) & 1u));
+            lo = static_cast<uint32_t>(
+                write_lane(static_cast<int>(static_cast<uint32_t>(bm)), i, static_cast<int>(lo)));
+            hi = static_cast<uint32_t>(
+                write_lane(static_cast<int>(static_cast<uint32_t>(bm >> 32)), i, static_cast<int>(hi)));
+        }
+        if (ln < 19u) {
+            svt[nv * kDenseWords + ln] = lo;
+            if (fcnt > 32u) svt[(nv + 1u) * kDenseWords + ln] = hi;
+        }
+        nv += fcnt > 32u ? 2u : 1u;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return nv;
+}
+
+// Dispatch on P (wave-uniform, 3..13).
+__device__ __forceinline__ uint32_t filter_windows_any(uint32_t P, cu32* W, uint32_t groups,
+                                                       uint32_t kv, int d, uint32_t* svt) {
+    switch (P) {
+        case 3: return filter_windows<3>(W, groups, kv, d, svt);
+        case 4: return filter_windows<4>(W, groups, kv, d, svt);
+        case 5: return filter_windows<5>(W, groups, kv, d, svt);
+        case 6: return filter_windows<6>(W, groups, kv, d, svt);
+        case 7: return filter_windows<7>(W, groups, kv, d, svt);
+        case 8: return filter_windows<8>(W, groups, kv, d, svt);
+        case 9: return filter_windows<9>(W, groups, kv, d, svt);
+        case 10: return filter_windows<10>(W, groups, kv, d, svt);
+        case 11: return filter_windows<11>(W, groups, kv, d, svt);
+        case 12: return filter_windows<12>(W, groups, kv, d, svt);
+        default: return filter_windows<13>(W, groups, kv, d, svt);
+    }
+}
+
+// Scan of the nv dense window groups filter_windows left in `svt`, for the
+// lane's group of 64 candidates (low = its last three prefix bases): per
+// group, the thresholds U_k walk through the lane's three prefix positions
+// (as in scan_group_shared) and the selection tree runs over the three
+// suffix positions.  Every word comes from LDS by broadcast reads, so the
+// loop issues no instruction with an SGPR operand.
+__device__ __forceinline__ uint64_t scan_filtered(uint32_t nv, const uint32_t* __restrict__ svt,
+                                                  uint32_t low, uint64_t alive) {
+    constexpr int S = 3;
+    constexpr int K = 64;
+    constexpr int N1 = K / 4;
+    uint32_t ch[3], cl[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const uint32_t b = (low >> (2 * (2 - q))) & 3u;
+        ch[q] = 0u - (b >> 1);
+        cl[q] = 0u - (b & 1u);
+    }
+    uint32_t found[K], top[N1];
+#pragma unroll
+    for (int c = 0; c < K; ++c) found[c] = 0u;
+#pragma unroll
+    for (int c = 0; c < N1; ++c) top[c] = 0u;
+    const uint4* sp = reinterpret_cast<const uint4*>(svt);
+    for (uint32_t g = 0; g < nv; ++g) {
+        uint32_t x[20];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const uint4 v = sp[g * (kDenseWords / 4) + i];
+            x[4 * i] = v.x;
+            x[4 * i + 1] = v.y;
+            x[4 * i + 2] = v.z;
+            x[4 * i + 3] = v.w;
+        }
+        // words: 0..6 U_k; 7..12 high plane of positions Q..Q+5; 13..18 low.
+        uint32_t m[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) m[q] = bop3<kOrXor>(x[7 + q] ^ ch[q], x[13 + q], cl[q]);
+        uint32_t v1[6], v2[5], t[4];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v1[k] = bop3<kMux>(m[0], x[k + 1], x[k]);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) v2[k] = bop3<kMux>(m[1], v1[k + 1], v1[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[k] = bop3<kMux>(m[2], v2[k + 1], v2[k]);
+        uint32_t sv[S][4];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const uint32_t h = x[10 + q], lo = x[16 + q];
+            sv[q][0] = bop3<0xFC>(h, lo, 0u);   // h | lo
+            sv[q][1] = bop3<0xF3>(h, lo, 0u);   // h | ~lo
+            sv[q][2] = bop3<0xCF>(h, lo, 0u);   // ~h | lo
+            sv[q][3] = bop3<0x3F>(h, lo, 0u);   // ~(h & lo)
+        }
+        select_accumulate<S>(t, sv, found, top);
+    }
+    return group_pass<S>(found, top) & alive;
+}
+
 // One sequence scan for one candidate per lane: whether some window is
 // within d of the l-mer `code` (motif code).  All L positions are counted
 // per lane by the carry-save tree of scan_group, with no selection tree; the
@@ -553,7 +781,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                                               uint32_t n_work, pms_dev_state* __restrict__ state,
                                               pms_dev_counters* __restrict__ ctr,
                                               uint32_t lds_stages, uint32_t* __restrict__ gq,
-                                              uint32_t gq_words) {
+                                              uint32_t gq_words, uint32_t flags) {
     typedef typename MaskOf<S>::type Mask;
     constexpr int K = 1 << (2 * S);
     constexpr uint32_t kNone = 0xffffffffu;
@@ -572,11 +800,12 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     const uint32_t gwave = blockIdx.x * uni(blockDim.x >> 6) + wave;
     uint32_t* const gw = gq + static_cast<size_t>(gwave) * gq_words;
     const uint32_t stages_cap = lds_stages + gq_words / kStageWords;
+    const bool filter = (flags & PMS_LAUNCH_NO_FILTER) == 0u;
 
     uint32_t cur = kNone, pending = 0, stash = kNone;
     bool more = true;
     uint64_t next = 0, end = 0;     // group numbers
-    uint64_t batches = 0, single_batches = 0;
+    uint64_t batches = 0, single_batches = 0, filtered = 0, filtered_groups = 0;
     uint64_t visits = 0;            // per lane
     uint32_t nob = 0;
     // Lane s: groups queued for stage s (low 16 bits) and singles (high 16).
@@ -786,8 +1015,20 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             // (Counted first with wave-uniform values only, then the
             // per-lane block data inside the branch that uses it: computed
             // ahead of the branch, it cost the general scan registers.)
+            // One block: the window filter first (dense window groups in
+            // svt; kNoFit when too many windows pass it).
+            uint32_t nv = kNoFit;
+            if (filter && P >= 3u && groups <= 64u) {
+                const uint64_t live = ballot(alive != 0);
+                if (live) {
+                    const uint32_t v0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(
+                        static_cast<int>(prefix >> 6), static_cast<int>(__builtin_ctzll(live))));
+                    if (ballot(alive != 0 && (prefix >> 6) != v0) == 0)
+                        nv = filter_windows_any(P, W + s * row, groups, v0, d, svt);
+                }
+            }
             bool blocks_fit = false;
-            if (P >= 3u && groups * 12u <= PMS_SVT_WORDS) {
+            if (nv == kNoFit && P >= 3u && groups * 12u <= PMS_SVT_WORDS) {
                 const uint32_t kmax = 64u / groups;
                 uint64_t todo = ballot(alive != 0);
                 for (uint32_t k = 0; todo != 0 && k < kmax; ++k) {
@@ -797,7 +1038,11 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 }
                 blocks_fit = todo == 0;
             }
-            if (blocks_fit) {
+            if (nv != kNoFit) {
+                pass = scan_filtered(nv, svt, prefix & 63u, alive);
+                ++filtered;
+                filtered_groups += nv;
+            } else if (blocks_fit) {
                 const uint32_t kmax = 64u / groups;
                 const uint32_t hi = prefix >> 6;
                 uint32_t kv = 0, tj = 64u, src = 0;
@@ -946,6 +1191,12 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         if (single_batches)
             atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->single_batches),
                       static_cast<unsigned long long>(single_batches));
+        if (filtered) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->filtered_batches),
+                      static_cast<unsigned long long>(filtered));
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->filtered_groups),
+                      static_cast<unsigned long long>(filtered_groups));
+        }
     }
 }
 
@@ -957,8 +1208,9 @@ extern "C" __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_p
 pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
                         const pms_work_item* __restrict__ work, uint32_t n_work,
                         pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
-                        uint32_t lds_stages, uint32_t* __restrict__ gq, uint32_t gq_words) {
-    search_groups<2>(insts, work, n_work, state, ctr, lds_stages, gq, gq_words);
+                        uint32_t lds_stages, uint32_t* __restrict__ gq, uint32_t gq_words,
+                        uint32_t flags) {
+    search_groups<2>(insts, work, n_work, state, ctr, lds_stages, gq, gq_words, flags);
 }
 
 // At most 4 wavefronts per workgroup: the 64 accumulators per lane need more
@@ -967,8 +1219,9 @@ extern "C" __global__ void __launch_bounds__(PMS_GROUP64_MAX_THREADS)
 pms_search_group64_kernel(const pms_dev_instance* __restrict__ insts,
                           const pms_work_item* __restrict__ work, uint32_t n_work,
                           pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
-                          uint32_t lds_stages, uint32_t* __restrict__ gq, uint32_t gq_words) {
-    search_groups<3>(insts, work, n_work, state, ctr, lds_stages, gq, gq_words);
+                          uint32_t lds_stages, uint32_t* __restrict__ gq, uint32_t gq_words,
+                          uint32_t flags) {
+    search_groups<3>(insts, work, n_work, state, ctr, lds_stages, gq, gq_words, flags);
 }
 
 namespace pms {
@@ -976,16 +1229,16 @@ namespace pms {
 hipError_t launch_search_group(const pms_dev_instance* insts, const pms_work_item* work,
                                uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
                                const GroupQueues& q, uint32_t grid, uint32_t wg_waves,
-                               hipStream_t stream, int suffix) {
+                               hipStream_t stream, int suffix, uint32_t flags) {
     const size_t lds = static_cast<size_t>(wg_waves) *
                        (q.lds_stages * stage_queue_words(suffix) + wave_fixed_words(suffix)) *
                        sizeof(uint32_t);
     if (suffix == 3)
         hipLaunchKernelGGL(pms_search_group64_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream,
-                           insts, work, n_work, state, ctr, q.lds_stages, q.gq, q.gq_words);
+                           insts, work, n_work, state, ctr, q.lds_stages, q.gq, q.gq_words, flags);
     else
         hipLaunchKernelGGL(pms_search_group_kernel, dim3(grid), dim3(64 * wg_waves), lds, stream,
-                           insts, work, n_work, state, ctr, q.lds_stages, q.gq, q.gq_words);
+                           insts, work, n_work, state, ctr, q.lds_stages, q.gq, q.gq_words, flags);
     return hipGetLastError();
 }
 

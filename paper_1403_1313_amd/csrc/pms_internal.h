@@ -97,6 +97,9 @@ hipError_t launch_noalloc_setup(void* base, const NoallocLayout& lay, uint32_t* 
 // Copies the instance's motif count to *dev_count.
 hipError_t launch_noalloc_count(const pms_dev_state* st, uint64_t* dev_count, hipStream_t stream);
 
+// Launch flags of the grouped kernels.
+#define PMS_LAUNCH_NO_FILTER 1u   // 64-candidate kernel: scan every window
+
 // Where a grouped launch keeps its stage queues: the first lds_stages in LDS,
 // the rest in gq (gq_words words per wavefront, grid x wg_waves wavefronts).
 struct GroupQueues {
@@ -109,7 +112,7 @@ struct GroupQueues {
 hipError_t launch_search_group(const pms_dev_instance* insts, const pms_work_item* work,
                                uint32_t n_work, pms_dev_state* state, pms_dev_counters* ctr,
                                const GroupQueues& q, uint32_t grid, uint32_t wg_waves,
-                               hipStream_t stream, int suffix);
+                               hipStream_t stream, int suffix, uint32_t flags);
 
 const void* search_group_kernel_symbol(int suffix);
 

@@ -5,6 +5,7 @@ been built this module raises ImportError; there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import threading
@@ -21,7 +22,7 @@ PMS_MAX_L, PMS_MAX_N, PMS_MAX_T = 16, 64, 1 << 17
 SYMBOLS = ["pms_solve", "pms_solve_ex", "pms_solve_intersect", "pms_solve_many", "pms_decode", "pms_status_string", "pms_last_error",
            "pms_set_config", "pms_get_config", "pms_autotune", "pms_last_stats",
            "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev",
-           "pms_valu_probe", "pms_solve_dev_noalloc"]
+           "pms_valu_probe", "pms_solve_dev_noalloc", "pms_shutdown"]
 PROBE_OPS = {"xor": 0, "bcnt": 1, "min3": 2, "or_sdwa": 3, "add": 4, "fma_f32": 5, "xor_vv": 6,
              "compare": 7, "mov_s": 8, "mov64_s": 9}
 
@@ -61,6 +62,7 @@ _INSTANCE_DT = _record_dtype(Instance)
 _RESULT_DT = _record_dtype(Result)
 
 VARIANT_AUTO, VARIANT_LANE, VARIANT_GROUP, VARIANT_GROUP64 = 0, 1, 2, 3
+FILTER_DEFAULT, FILTER_ON, FILTER_OFF = 0, 1, 2
 INPUT_MASK_N, INPUT_BOTH_STRANDS = 1, 2
 VARIANT_NAMES = {1: "lane", 2: "group16", 3: "group64"}
 LAYOUT_PLANES, LAYOUT_BITSLICED = 0, 1
@@ -69,7 +71,7 @@ LAYOUT_PLANES, LAYOUT_BITSLICED = 0, 1
 class Config(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32), ("wg_waves", ctypes.c_uint32),
                 ("wgs_per_cu", ctypes.c_uint32), ("tail_split", ctypes.c_uint32),
-                ("variant", ctypes.c_uint32)]
+                ("variant", ctypes.c_uint32), ("filter", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -83,7 +85,8 @@ class Stats(ctypes.Structure):
                 ("chunk", ctypes.c_uint32), ("reruns", ctypes.c_uint32),
                 ("variant", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("host_prep_ms", ctypes.c_double), ("host_finish_ms", ctypes.c_double),
-                ("single_batches", ctypes.c_uint64)]
+                ("single_batches", ctypes.c_uint64), ("filtered_batches", ctypes.c_uint64),
+                ("filtered_groups", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))
@@ -114,7 +117,8 @@ class DevState(ctypes.Structure):
 class DevCounters(ctypes.Structure):
     _fields_ = [("next_item", ctypes.c_uint32), ("error", ctypes.c_uint32),
                 ("batches", ctypes.c_uint64), ("t_start", ctypes.c_uint64),
-                ("single_batches", ctypes.c_uint64)]
+                ("single_batches", ctypes.c_uint64), ("filtered_batches", ctypes.c_uint64),
+                ("filtered_groups", ctypes.c_uint64)]
 
 
 def _load():
@@ -153,6 +157,7 @@ def _load():
         "pms_solve_dev": ([vp, i32, i32, i32, i32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
         "pms_valu_probe": ([ctypes.c_int, i32, i32, P(ProbeResult)], ctypes.c_int),
         "pms_solve_dev_noalloc": ([vp, i32, i32, i32, i32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
+        "pms_shutdown": ([], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -162,6 +167,17 @@ def _load():
 
 
 _lib = _load()
+
+
+def shutdown() -> int:
+    """pms_shutdown: releases the library's device resources (status code;
+    a later call creates them again)."""
+    return int(_lib.pms_shutdown())
+
+
+# The library's streams, events, graph and buffers are released before the
+# interpreter exits, so none of them outlives the HIP runtime's own teardown.
+atexit.register(shutdown)
 
 
 def lib():
@@ -337,10 +353,10 @@ def decode(code: int, l: int) -> str:
     return buf.raw[:l].decode()
 
 
-def set_config(chunk=0, wg_waves=0, wgs_per_cu=0, tail_split=0, variant=0, reset=False):
+def set_config(chunk=0, wg_waves=0, wgs_per_cu=0, tail_split=0, variant=0, filter=0, reset=False):
     if reset:
         return _check(_lib.pms_set_config(None))
-    cfg = Config(chunk, wg_waves, wgs_per_cu, tail_split, variant)
+    cfg = Config(chunk, wg_waves, wgs_per_cu, tail_split, variant, filter)
     return _check(_lib.pms_set_config(ctypes.byref(cfg)))
 
 

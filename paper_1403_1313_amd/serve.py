@@ -67,7 +67,7 @@ class Result:
 class _Req:
     __slots__ = ("rid", "seqs", "l", "d", "n", "t", "arrival", "future", "slot", "dev_seqs",
                  "dev_win", "dev_out", "cap", "bytes", "total", "cursor", "inflight", "steps",
-                 "reruns", "admitted", "cost_per_cand", "stride", "h_out")
+                 "reruns", "admitted", "cost_per_cand", "stride", "h_out", "failed")
 
     def __init__(self, rid, seqs, l, d, arrival, future):
         self.rid = rid
@@ -89,6 +89,7 @@ class _Req:
         self.reruns = 0
         self.admitted = 0.0
         self.h_out = None   # pinned copy of the first codes, made right after the last step
+        self.failed = False  # its future holds an error; slot kept until its steps retire
         self.bytes = self._bytes()
 
     def _bytes(self) -> int:
@@ -103,8 +104,10 @@ class _StepBuf:
         self.h_work = torch.zeros(max_items * 16, dtype=torch.uint8).pin_memory()
         self.d_work = torch.zeros(max_items * 16, dtype=torch.uint8, device=dev)
         self.d_ctr = torch.zeros(ctypes.sizeof(nat.DevCounters) // 8, dtype=torch.int64, device=dev)
+        self.h_ctr = torch.zeros(ctypes.sizeof(nat.DevCounters) // 8, dtype=torch.int64).pin_memory()
         self.h_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8).pin_memory()
         self.event = None           # end of the search launch (timed)
+        self.launched = 0.0         # host time of the launch (step watchdog)
         self.done = None            # state snapshot copied to the host
         self.start = None
         self.compares = 0.0         # estimated window compares of the step
@@ -113,14 +116,27 @@ class _StepBuf:
         self.items_per_req: Dict[int, int] = {}
 
 
+class StepTimeout(RuntimeError):
+    """A step did not complete within the server's step timeout."""
+
+
 class Server:
-    """Continuous-batching server.  ``submit`` returns a Future of ``Result``."""
+    """Continuous-batching server.  ``submit`` returns a Future of ``Result``.
+
+    Failures: a request whose window table cannot be built fails alone; a
+    step whose launch fails, or whose kernel reports an error (an instance it
+    could not run), fails the requests it held and the server goes on with
+    the others.  A step that has not completed ``step_timeout_s`` after it
+    was launched fails every pending request with ``StepTimeout`` and stops
+    the server: the device queue is then blocked behind that step.
+    """
 
     def __init__(self, mem_budget: int = 256 << 20, step_ms: float = 2.0,
                  max_inflight: int = 2, compares_per_s: float = 2.5e14,
                  device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
                  items_per_step: int = 8192, oldest_share: float = 0.5,
-                 min_step_ms: Optional[float] = None, backlog_share: float = 0.25):
+                 min_step_ms: Optional[float] = None, backlog_share: float = 0.25,
+                 step_timeout_s: float = 60.0):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)
@@ -145,6 +161,11 @@ class Server:
         # Steps run a grouped kernel, whose windows are bit-sliced: 64
         # candidates per lane, or 16 when a step holds an l = 2 request.
         self.config = dict(config or {})
+        if self.config.get("variant", nat.VARIANT_AUTO) not in (
+                nat.VARIANT_AUTO, nat.VARIANT_GROUP, nat.VARIANT_GROUP64):
+            raise ValueError("the server's window tables are bit-sliced: variant must be "
+                             "AUTO, GROUP or GROUP64")
+        self.step_timeout_s = float(step_timeout_s)
         self.reserve = reserve  # fixed first output reservation (tests of the rerun path)
         self.d_insts = torch.zeros(MAX_SLOTS * 40, dtype=torch.uint8, device=self.dev)
         self.d_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8, device=self.dev)
@@ -224,17 +245,49 @@ class Server:
 
     def _admit(self):
         """Moves waiting requests in, oldest first, while memory and slots allow."""
-        torch = self.torch
         while self.waiting and self.free_slots:
             req = self.waiting[0]
             if self.mem_used + req.bytes > self.mem_budget and (self.active or self.inflight):
                 self.stats["admission_waits"] += 1
                 return
             self.waiting.popleft()
-            self._upload(req)
+            try:
+                self._upload(req)
+            except nat.PmsError as e:
+                # This request alone: its slot was never referenced by a step.
+                self.free_slots.append(req.slot)
+                req.dev_seqs = req.dev_win = req.dev_out = None
+                self.stats["failed_admissions"] += 1
+                req.future.set_exception(e)
+                continue
             self.active.append(req)
             self.mem_used += req.bytes
             req.admitted = time.perf_counter()
+
+    def _fail(self, reqs, exc: BaseException):
+        """Fails these requests: each future gets `exc` now; a request's slot
+        and memory are released once no step in flight refers to them."""
+        for r in reqs:
+            if r.failed:
+                continue
+            r.failed = True
+            if r in self.active:
+                self.active.remove(r)
+            if not r.future.done():
+                r.future.set_exception(exc)
+            self.stats["failed"] += 1
+            if r.inflight == 0:
+                self._release(r)
+
+    def _release(self, r: _Req):
+        self.free_slots.append(r.slot)
+        self.mem_used -= r.bytes
+        r.dev_seqs = r.dev_win = r.dev_out = None
+        r.h_out = None
+
+    def _launch_max_n(self, reqs) -> int:
+        """The largest n of a step (it sizes the kernel's stage queues)."""
+        return max(r.n for r in reqs)
 
     def _upload(self, req: _Req):
         torch = self.torch
@@ -354,21 +407,34 @@ class Server:
             return False
         self.idle_bufs.pop()
         torch = self.torch
-        max_n = max(r.n for r in buf.reqs)
+        max_n = self._launch_max_n(buf.reqs)
         cfg = dict(self.config)
-        if "variant" not in cfg:
-            cfg["variant"] = nat.VARIANT_GROUP64 if min(r.l for r in buf.reqs) >= 3 else nat.VARIANT_GROUP
+        # 64 candidates per lane need l >= 3: a step holding an l = 2
+        # request runs the 16-candidate kernel (same bit-sliced windows).
+        if min(r.l for r in buf.reqs) < 3:
+            cfg["variant"] = nat.VARIANT_GROUP
+        elif cfg.get("variant", nat.VARIANT_AUTO) == nat.VARIANT_AUTO:
+            cfg["variant"] = nat.VARIANT_GROUP64
         with torch.cuda.stream(self.stream):
             buf.d_work[:n_items * 16].copy_(buf.h_work[:n_items * 16], non_blocking=True)
             buf.d_ctr.zero_()
             buf.start = torch.cuda.Event(enable_timing=True)
             buf.start.record(self.stream)
-        nat.step_launch(self.d_insts, MAX_SLOTS, max_n, buf.d_work, n_items, self.d_state,
-                        buf.d_ctr, config=cfg, stream=self.stream)
+        try:
+            nat.step_launch(self.d_insts, MAX_SLOTS, max_n, buf.d_work, n_items, self.d_state,
+                            buf.d_ctr, config=cfg, stream=self.stream)
+        except nat.PmsError as e:
+            # Nothing of this step runs: its requests fail, the others go on.
+            self.stats["failed_steps"] += 1
+            reqs, buf.reqs = buf.reqs, []
+            self.idle_bufs.append(buf)
+            self._fail(reqs, e)
+            return True
         with torch.cuda.stream(self.stream):
             buf.event = torch.cuda.Event(enable_timing=True)
             buf.event.record(self.stream)
             buf.h_state.copy_(self.d_state, non_blocking=True)
+            buf.h_ctr.copy_(buf.d_ctr, non_blocking=True)
             # Requests whose last candidates are in this step: their first
             # codes come back on this stream, before the next step's kernel
             # takes every compute unit (a copy queued behind it would wait
@@ -384,6 +450,7 @@ class Server:
         for r in buf.reqs:
             r.inflight += 1
             r.steps += 1
+        buf.launched = time.perf_counter()
         self.inflight.append(buf)
         self.stats["steps"] += 1
         self.stats["items"] += n_items
@@ -402,13 +469,30 @@ class Server:
         states = np.frombuffer(buf.h_state.numpy().tobytes(), dtype=[
             ("count", "<u8"), ("visits", "<u8"), ("t_done", "<u8"), ("items_left", "<u4"),
             ("reserved", "<u4")])
-        for r in buf.reqs:
+        ctr = nat.DevCounters.from_buffer_copy(buf.h_ctr.numpy().tobytes())
+        reqs, buf.reqs = buf.reqs, []
+        self.idle_bufs.append(buf)
+        if ctr.error:
+            # The kernel skipped an instance it could not run (pms_dev_counters.error):
+            # every request of the step is in doubt.
+            self.stats["failed_steps"] += 1
+            for r in reqs:
+                r.inflight -= 1
+                if r.failed and r.inflight == 0:
+                    self._release(r)
+            self._fail([r for r in reqs if not r.failed],
+                       nat.PmsError(nat.PMS_ERR_DEVICE,
+                                    "a search step reported an instance it could not run"))
+            return
+        for r in reqs:
             r.inflight -= 1
+            if r.failed:
+                if r.inflight == 0:
+                    self._release(r)
+                continue
             if r.cursor >= r.total and r.inflight == 0:
                 self._finish(r, int(states[r.slot]["count"]), int(states[r.slot]["visits"]),
                              buf.event)
-        buf.reqs = []
-        self.idle_bufs.append(buf)
 
     def _finish(self, r: _Req, count: int, visits: int, done_event):
         torch = self.torch
@@ -472,6 +556,21 @@ class Server:
         self.stats["completed"] += 1
         r.future.set_result(res)
 
+    def _wait_step(self, buf: _StepBuf) -> bool:
+        """Waits for a step to complete, up to the step timeout from its
+        launch (polling: an event wait could not be abandoned)."""
+        deadline = buf.launched + self.step_timeout_s
+        spins = 0
+        while not buf.done.query():
+            now = time.perf_counter()
+            if now > deadline:
+                self.stats["step_timeouts"] += 1
+                raise StepTimeout(f"a search step has not completed {self.step_timeout_s:g} s "
+                                  "after its launch")
+            spins += 1
+            time.sleep(0 if spins < 200 else 50e-6)
+        return True
+
     def _fail_all(self, exc: BaseException):
         for r in list(self.active) + list(self.waiting) + [f[0] for f in self.finishing]:
             if not r.future.done():
@@ -497,7 +596,7 @@ class Server:
                 self._complete(block=False)
                 if self.inflight:
                     head = self.inflight[0]
-                    if head.done.query() or not launched:
+                    if head.done.query() or (not launched and self._wait_step(head)):
                         self.inflight.popleft()
                         self._retire(head)
                 elif self.finishing and not launched:
@@ -505,4 +604,5 @@ class Server:
         except BaseException as e:  # noqa: BLE001 - every request learns of the failure
             self.error = e
             with self.cv:
+                self.running = False
                 self._fail_all(e)

@@ -6,6 +6,7 @@ synthetic inputs of ``fmgen``; nothing is taken from the GPU library.
   python tests/golden/make_golden.py plain_8_1 plain_11_3          # brute, seeds 0-4
   python tests/golden/make_golden.py plain_15_4 --seeds 0 --mode brute
   python tests/golden/make_golden.py batched --mode skip
+  python tests/golden/make_golden.py serving --mode skip
 
 Each record holds the instance recipe, the oracle mode that produced it, the
 motif count, the SHA-256 of the ascending little-endian uint32 candidate
@@ -80,6 +81,9 @@ def main():
         if cfg == "batched":
             specs = fmgen.batched_specs(args.count)
             recipe = "fmgen.batched_specs(256, master_seed=1403)"
+        elif cfg == "serving":
+            specs = fmgen.serving_check_specs()
+            recipe = "fmgen.serving_check_specs()"
         else:
             shape = fmgen.PLAIN[cfg]
             specs = [fmgen.Spec(seed=s, **shape) for s in args.seeds]
@@ -89,7 +93,7 @@ def main():
             if key in old and (old[key]["mode"] == "brute" or args.mode == "skip"):
                 continue
             listed = args.max_listed if args.max_listed is not None else (
-                64 if cfg == "batched" else MAX_LISTED)
+                64 if cfg in ("batched", "serving") else MAX_LISTED)
             rec = record(spec, args.mode, args.threads, listed)
             old[key] = rec
             print(f"{cfg} #{q} l={spec.l} d={spec.d} n={spec.n} t={spec.t} "

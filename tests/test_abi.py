@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 17
+    assert len(names) == 18
     assert sorted(nat.SYMBOLS) == names
     lib = ctypes.CDLL(nat.LIB_PATH)
     for name in names:
@@ -36,14 +36,16 @@ def test_struct_layouts_match_header(tmp_path):
     fields = {
         "pms_instance": ["seqs", "n", "t", "l", "d", "out_motifs", "capacity"],
         "pms_result": ["status", "count", "latency_ms"],
-        "pms_config": ["chunk", "wg_waves", "wgs_per_cu", "tail_split", "variant"],
+        "pms_config": ["chunk", "wg_waves", "wgs_per_cu", "tail_split", "variant", "filter"],
         "pms_stats": ["kernel_ms", "windows_ms", "seq_visits", "batches", "window_compares",
                       "candidate_slots", "grid", "wg_waves", "chunk", "reruns", "variant",
-                      "host_prep_ms", "host_finish_ms", "single_batches"],
+                      "host_prep_ms", "host_finish_ms", "single_batches", "filtered_batches",
+                      "filtered_groups"],
         "pms_dev_instance": ["windows", "out", "out_cap", "n", "nw_stride", "l", "d"],
         "pms_work_item": ["begin", "len", "inst"],
         "pms_dev_state": ["count", "visits", "t_done", "items_left"],
-        "pms_dev_counters": ["next_item", "error", "batches", "t_start", "single_batches"],
+        "pms_dev_counters": ["next_item", "error", "batches", "t_start", "single_batches",
+                             "filtered_batches", "filtered_groups"],
         "pms_probe_result": ["lane_ops_per_s", "ms", "sclk_mhz", "lane_ops_per_clk_per_cu",
                              "compute_units"],
     }
@@ -176,9 +178,11 @@ def test_config_validation():
     assert nat.get_config()["chunk"] == 4096 and nat.get_config()["wg_waves"] == 2
     nat.set_config(reset=True)
     assert nat.get_config() == {"chunk": 16384, "wg_waves": 4, "wgs_per_cu": 0, "tail_split": 0,
-                                "variant": 0}
+                                "variant": 0, "filter": 0}
     with pytest.raises(nat.PmsError):
         nat.set_config(variant=4)
+    with pytest.raises(nat.PmsError):
+        nat.set_config(filter=3)
 
 
 def test_injected_failure_propagates(monkeypatch):
@@ -280,3 +284,14 @@ def test_solve_dev_noalloc_rejects_bad_arguments():
     text = open(HEADER).read()
     assert re.search(r"#define PMS_NOALLOC_SCRATCH_BYTES \(128u << 20\)", text)
     del cnt
+
+
+def test_shutdown_without_device_work():
+    """pms_shutdown before any device work makes no HIP call and succeeds;
+    twice in a row as well (the binding also runs it at exit)."""
+    code = ("import paper_1403_1313_amd.native as n\n"
+            "assert n.shutdown() == 0 and n.shutdown() == 0\n"
+            "print('ok')\n")
+    out = subprocess.run([__import__("sys").executable, "-c", code], cwd=ROOT, check=True,
+                         capture_output=True, text=True).stdout.strip()
+    assert out == "ok"
