@@ -56,6 +56,7 @@ constexpr uint32_t kAnd3 = 0x80;     // a & b & c
 constexpr uint32_t kNandOr = 0x1F;   // ~(a & (b | c))
 constexpr uint32_t kNorAnd = 0x07;   // ~(a | (b & c))
 constexpr uint32_t kOrXor = 0xF6;    // a | (b ^ c)
+constexpr uint32_t kAndN = 0x30;     // a & ~b
 
 // Bit-sliced sum of P one-bit vectors plus a wave-uniform bias B < 32 given
 // as five all-ones / all-zero masks bias[i] = bit i of B:
@@ -134,7 +135,7 @@ __device__ __forceinline__ void suffix_vectors(uint32_t h, uint32_t lo, uint32_t
 // U_j[..][k] = [mismatches + s_1 + .. + s_j <= d - k].  The last level is
 // folded into the accumulators: a candidate has a good window where
 //   U_{S-1}[..][1]  |  (~s_S[bS] & U_{S-1}[..][0]).
-template <int S>
+template <int S, bool First = false>
 __device__ __forceinline__ void select_accumulate(const uint32_t (&t)[4], const uint32_t (&sv)[S][4],
                                                   uint32_t (&found)[1 << (2 * S)],
                                                   uint32_t (&top)[1 << (2 * S - 2)]) {
@@ -164,10 +165,17 @@ __device__ __forceinline__ void select_accumulate(const uint32_t (&t)[4], const 
     }
 #pragma unroll
     for (int n = 0; n < N1; ++n) {
-        top[n] |= u[n][1];
+        if constexpr (First) {
+            // The first window group sets the accumulators (no zeroing).
+            top[n] = u[n][1];
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            found[n * 4 + b] = bop3<kOrAndN>(found[n * 4 + b], u[n][0], sv[S - 1][b]);
+            for (int b = 0; b < 4; ++b) found[n * 4 + b] = bop3<kAndN>(u[n][0], sv[S - 1][b], 0u);
+        } else {
+            top[n] |= u[n][1];
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                found[n * 4 + b] = bop3<kOrAndN>(found[n * 4 + b], u[n][0], sv[S - 1][b]);
+        }
     }
 }
 
@@ -481,38 +489,41 @@ __device__ __forceinline__ uint64_t scan_group_shared_any(uint32_t P, cu32* W, u
     }
 }
 
-// Window filter for 64 groups that all lie in one block of 64 consecutive
-// groups (they share their first Q = P - 3 bases, the block number kv).  A
-// window whose mismatch count over the shared bases exceeds d is farther than
-// d from every candidate of the block, so only the windows with
-// U_0 = [shared count <= d] set can matter; the others cannot change any
-// candidate's result (an exact filter on top of the enhanced rule, which it
-// leaves unchanged: the same candidates reach the same sequences).
+// Window filter for a batch of 64 groups whose live lanes fall into nb
+// blocks of 64 consecutive groups (each block shares its first Q = P - 3
+// bases).  A window whose mismatch count over a block's shared bases exceeds
+// d is farther than d from every candidate of that block; a window farther
+// for every block of the batch cannot change any candidate's result, so only
+// the windows with U_0 = [shared count <= d] set for some block are scanned
+// (an exact filter on top of the enhanced rule, which it leaves unchanged:
+// the same candidates reach the same sequences).
 //
-// filter_windows builds the block's thresholds (table lane j < groups: U_0..
-// U_6 of window group j, as in scan_group_shared, and the window group's
-// plane words of the six unshared positions: 3 lane, 3 suffix, high then low
-// plane), then re-slices the windows with U_0 set into dense 32-window
-// groups in the wavefront's LDS table `svt`, 20 words each:
-//   U_0..U_6, high plane of the six positions, low plane of the six.
-//  * Windows are taken 64 at a time (two window groups, one per lane); the
-//    survivors move to consecutive lanes with one ds_permute (a rotation of
-//    the stable compaction order, so that no two lanes collide) and gather
-//    until 64 are pending.
-//  * 64 pending windows (or the rest, at the end) are re-sliced: each lane
-//    fetches its window's 19 words from the table lane (ds_bpermute) and one
-//    ballot per word forms the new bit-sliced words.  Lanes past the pending
+// filter_windows builds the blocks' thresholds in the table lanes of
+// scan_group_shared (lane b * groups + j: block b, window group j; U_0..U_6)
+// with the window group's plane words of the six unshared positions (3 lane,
+// 3 suffix; high plane, then low), and re-slices the windows that pass into
+// dense 32-window groups in the wavefront's LDS table `svt`, 12 + 8 nb words
+// each: the 12 plane words, then U_0..U_6 (and one spare word) per block.
+//  * The union mask of each window group is collected in lane j (one
+//    ds_bpermute per block); the lanes' offsets in the list of passing
+//    windows come from bit-serial ballots of their counts, and each lane
+//    writes the numbers of its passing windows into a 64-entry LDS list,
+//    64 list positions at a time.
+//  * 64 listed windows (or the rest, at the end) are re-sliced: each lane
+//    fetches its window's words from the table lanes (ds_bpermute) and one
+//    ballot per word forms the new bit-sliced words.  Lanes past the listed
 //    count give all-zero words: U_0 = 0 there, which no candidate passes.
 // Returns the number of dense groups, or kNoFit when they would not fit in
 // the table (the caller then scans every window).  No per-candidate state
 // is live here, which keeps the register budget of scan_filtered's loop.
-// Requires 3 <= P <= 13 and groups <= 64.
+// Requires 3 <= P <= 13, nb * groups <= 64 and nb <= kFilterBlocks.
 constexpr uint32_t kNoFit = 0xffffffffu;
-constexpr uint32_t kDenseWords = 20u;
-constexpr uint32_t kDenseMax = PMS_SVT_WORDS / kDenseWords;
+constexpr uint32_t kListWords = 64u;
+constexpr uint32_t kFilterBlocks = 4u;
 
 template <int P>
-__device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uint32_t kv, int d,
+__device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uint32_t nb,
+                                                   uint32_t kv, uint32_t tj, int d,
                                                    uint32_t* __restrict__ svt) {
     constexpr int L = P + 3;
     constexpr int Q = P - 3;
@@ -529,9 +540,9 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
         for (int p = 0; p < (Q > 0 ? Q : 1); ++p) m[p] = 0u;
 #pragma unroll
         for (int i = 0; i < 12; ++i) pw[i] = 0u;
-        const bool table = ln < groups;
+        const bool table = tj < groups;
         if (table) {
-            const uint32_t* row = (const uint32_t*)(W) + ln * (2u * L);
+            const uint32_t* row = (const uint32_t*)(W) + tj * (2u * L);
 #pragma unroll
             for (int p = 0; p < Q; ++p) {
                 const uint32_t b = (kv >> (2 * (Q - 1 - p))) & 3u;
@@ -545,7 +556,7 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
         }
         uint32_t c[5];
         count_bits<Q>(m, bias, c);
-        // Lanes past the last window group hold no windows.
+        // Lanes that are no table lane hold no windows.
         const uint32_t on = table ? ~0u : 0u;
         u[0] = on & ~(c[4] & (c[3] | c[2]));
         u[1] = on & ~(c[4] & (c[3] | c[2] | (c[1] & c[0])));
@@ -555,70 +566,81 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
         u[5] = on & ~(c[4] | (c[3] & c[2] & c[1] & c[0]));
         u[6] = on & ~(c[4] | (c[3] & c[2] & c[1]));
     }
-    // Windows to keep: the sum over lanes of popcount(U_0), bit by bit.
-    const uint32_t pc = static_cast<uint32_t>(__builtin_popcount(u[0]));
-    uint32_t total = 0;
+    // Lane j < groups: the windows of window group j that pass for some block.
+    uint32_t um = 0;
+    for (uint32_t b = 0; b < nb; ++b)
+        um |= static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(
+            static_cast<int>((b * groups + ln) << 2), static_cast<int>(u[0])));
+    um = ln < groups ? um : 0u;
+    // Total and each lane's offset in the list, from the counts' bits.
+    const uint32_t pc = static_cast<uint32_t>(__builtin_popcount(um));
+    uint32_t total = 0, off = 0;
 #pragma unroll
-    for (int b = 0; b < 6; ++b)
-        total += static_cast<uint32_t>(__builtin_popcountll(ballot((pc >> b) & 1u))) << b;
+    for (int b = 0; b < 6; ++b) {
+        const uint64_t bm = ballot((pc >> b) & 1u);
+        total += static_cast<uint32_t>(__builtin_popcountll(bm)) << b;
+        off += rank_below(bm) << b;
+    }
+    const uint32_t stride = 12u + 8u * nb;
     const uint32_t dense = (total + 31u) >> 5;
-    if (dense > kDenseMax) return kNoFit;
-    const uint32_t slabs = (groups + 1u) >> 1;
-    uint32_t sb = 0, r = 0, nv = 0;   // next slab; windows pending; dense groups written
-    uint32_t pend = 0;                // lanes < r: a pending window number
-    for (;;) {
-        uint32_t fidx, fcnt;
-        if (sb < slabs) {
-            // Slab sb: windows 64 sb + lane, of window groups 2 sb and 2 sb + 1.
-            const uint32_t j = 2u * sb + (ln >> 5);
-            const uint32_t m0 = static_cast<uint32_t>(
-                __builtin_amdgcn_ds_bpermute(static_cast<int>(j << 2), static_cast<int>(u[0])));
-            const bool hit = ((m0 >> (ln & 31u)) & 1u) != 0u;
-            const uint64_t hm = ballot(hit);
-            const uint32_t w = 64u * sb + ln;
-            ++sb;
-            if (hm == 0) continue;
-            const uint32_t cnt = static_cast<uint32_t>(__builtin_popcountll(hm));
-            const uint32_t rk = hit ? rank_below(hm) : cnt + rank_below(~hm);
-            const uint32_t got = static_cast<uint32_t>(__builtin_amdgcn_ds_permute(
-                static_cast<int>(((r + rk) & 63u) << 2), static_cast<int>(w)));
-            if (r + cnt < 64u) {
-                if (((ln - r) & 63u) < cnt) pend = got;
-                r += cnt;
-                continue;
+    if (dense * stride + kListWords > PMS_SVT_WORDS) return kNoFit;
+    uint32_t* const list = svt + (PMS_SVT_WORDS - kListWords);
+    uint32_t nv = 0;
+    for (uint32_t base = 0; base < total; base += 64u) {
+        // List positions [base, base + 64): each lane writes its passing
+        // windows' numbers in order.
+        {
+            uint32_t mm = um, at = off;
+            while (mm != 0u && at < base + 64u) {
+                const uint32_t bit = static_cast<uint32_t>(__builtin_ctz(mm));
+                if (at >= base) list[at - base] = 32u * ln + bit;
+                mm &= mm - 1u;
+                ++at;
             }
-            fidx = ln >= r ? got : pend;
-            fcnt = 64u;
-            r = r + cnt - 64u;
-            pend = got;
-        } else {
-            if (r == 0) break;
-            fidx = pend;
-            fcnt = r;
-            r = 0;
         }
-        // Re-slice the fcnt windows held by lanes 0 .. fcnt-1: word i of the
-        // dense group(s) is ballot i, written by lane i.
-        const bool valid = ln < fcnt;
-        const uint32_t wi = valid ? fidx : 0u;
-        const int src = static_cast<int>((wi >> 5) << 2);
-        const uint32_t bit = wi & 31u;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t cnt = total - base < 64u ? total - base : 64u;
+        const bool valid = ln < cnt;
+        const uint32_t wi = valid ? list[ln] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t g = wi >> 5, bit = wi & 31u;
         uint32_t lo = 0, hi = 0;
+        // Plane words: from lane g (block 0's table lane of window group g).
+        uint32_t x[12];
 #pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const uint32_t x = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(
-                src, static_cast<int>(i < 7 ? u[i] : pw[i - 7])));
-            const uint64_t bm = ballot(valid && ((x >> bit) & 1u));
-            lo = static_cast<uint32_t>(
-                write_lane(static_cast<int>(static_cast<uint32_t>(bm)), i, static_cast<int>(lo)));
-            hi = static_cast<uint32_t>(
-                write_lane(static_cast<int>(static_cast<uint32_t>(bm >> 32)), i, static_cast<int>(hi)));
+        for (int i = 0; i < 12; ++i)
+            x[i] = static_cast<uint32_t>(
+                __builtin_amdgcn_ds_bpermute(static_cast<int>(g << 2), static_cast<int>(pw[i])));
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const uint64_t bm = ballot(valid && ((x[i] >> bit) & 1u));
+            lo = static_cast<uint32_t>(write_lane(static_cast<int>(static_cast<uint32_t>(bm)), i,
+                                                  static_cast<int>(lo)));
+            hi = static_cast<uint32_t>(write_lane(static_cast<int>(static_cast<uint32_t>(bm >> 32)),
+                                                  i, static_cast<int>(hi)));
         }
-        if (ln < 19u) {
-            svt[nv * kDenseWords + ln] = lo;
-            if (fcnt > 32u) svt[(nv + 1u) * kDenseWords + ln] = hi;
+        // Thresholds of each block: from lane b * groups + g.
+        for (uint32_t b = 0; b < nb; ++b) {
+            const int src = static_cast<int>((b * groups + g) << 2);
+            uint32_t y[7];
+#pragma unroll
+            for (int k = 0; k < 7; ++k)
+                y[k] = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(src, static_cast<int>(u[k])));
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                const uint64_t bm = ballot(valid && ((y[k] >> bit) & 1u));
+                const int at = static_cast<int>(12u + 8u * b) + k;
+                lo = static_cast<uint32_t>(write_lane(static_cast<int>(static_cast<uint32_t>(bm)), at,
+                                                      static_cast<int>(lo)));
+                hi = static_cast<uint32_t>(write_lane(
+                    static_cast<int>(static_cast<uint32_t>(bm >> 32)), at, static_cast<int>(hi)));
+            }
         }
-        nv += fcnt > 32u ? 2u : 1u;
+        if (ln < stride) {
+            svt[nv * stride + ln] = lo;
+            if (cnt > 32u) svt[(nv + 1u) * stride + ln] = hi;
+        }
+        nv += cnt > 32u ? 2u : 1u;
     }
     __builtin_amdgcn_wave_barrier();
     return nv;
@@ -626,33 +648,38 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
 
 // Dispatch on P (wave-uniform, 3..13).
 __device__ __forceinline__ uint32_t filter_windows_any(uint32_t P, cu32* W, uint32_t groups,
-                                                       uint32_t kv, int d, uint32_t* svt) {
+                                                       uint32_t nb, uint32_t kv, uint32_t tj,
+                                                       int d, uint32_t* svt) {
     switch (P) {
-        case 3: return filter_windows<3>(W, groups, kv, d, svt);
-        case 4: return filter_windows<4>(W, groups, kv, d, svt);
-        case 5: return filter_windows<5>(W, groups, kv, d, svt);
-        case 6: return filter_windows<6>(W, groups, kv, d, svt);
-        case 7: return filter_windows<7>(W, groups, kv, d, svt);
-        case 8: return filter_windows<8>(W, groups, kv, d, svt);
-        case 9: return filter_windows<9>(W, groups, kv, d, svt);
-        case 10: return filter_windows<10>(W, groups, kv, d, svt);
-        case 11: return filter_windows<11>(W, groups, kv, d, svt);
-        case 12: return filter_windows<12>(W, groups, kv, d, svt);
-        default: return filter_windows<13>(W, groups, kv, d, svt);
+        case 3: return filter_windows<3>(W, groups, nb, kv, tj, d, svt);
+        case 4: return filter_windows<4>(W, groups, nb, kv, tj, d, svt);
+        case 5: return filter_windows<5>(W, groups, nb, kv, tj, d, svt);
+        case 6: return filter_windows<6>(W, groups, nb, kv, tj, d, svt);
+        case 7: return filter_windows<7>(W, groups, nb, kv, tj, d, svt);
+        case 8: return filter_windows<8>(W, groups, nb, kv, tj, d, svt);
+        case 9: return filter_windows<9>(W, groups, nb, kv, tj, d, svt);
+        case 10: return filter_windows<10>(W, groups, nb, kv, tj, d, svt);
+        case 11: return filter_windows<11>(W, groups, nb, kv, tj, d, svt);
+        case 12: return filter_windows<12>(W, groups, nb, kv, tj, d, svt);
+        default: return filter_windows<13>(W, groups, nb, kv, tj, d, svt);
     }
 }
 
-// Scan of the nv dense window groups filter_windows left in `svt`, for the
-// lane's group of 64 candidates (low = its last three prefix bases): per
-// group, the thresholds U_k walk through the lane's three prefix positions
-// (as in scan_group_shared) and the selection tree runs over the three
-// suffix positions.  Every word comes from LDS by broadcast reads, so the
-// loop issues no instruction with an SGPR operand.
-__device__ __forceinline__ uint64_t scan_filtered(uint32_t nv, const uint32_t* __restrict__ svt,
-                                                  uint32_t low, uint64_t alive) {
+// Scan of the nv dense window groups filter_windows left in `svt` (stride
+// words each) for the lane's group of 64 candidates: myb = the lane's block
+// in the batch, low = its last three prefix bases.  Per group the block's
+// thresholds U_k walk through the lane's three prefix positions (as in
+// scan_group_shared) and the selection tree runs over the three suffix
+// positions.  Every word comes from LDS (the plane words by broadcast reads,
+// the thresholds from the lane's block), so the loop issues no instruction
+// with an SGPR operand.
+__device__ __forceinline__ uint64_t scan_filtered(uint32_t nv, uint32_t stride, uint32_t myb,
+                                                  const uint32_t* __restrict__ svt, uint32_t low,
+                                                  uint64_t alive) {
     constexpr int S = 3;
     constexpr int K = 64;
     constexpr int N1 = K / 4;
+    if (nv == 0) return 0;
     uint32_t ch[3], cl[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -661,28 +688,34 @@ __device__ __forceinline__ uint64_t scan_filtered(uint32_t nv, const uint32_t* _
         cl[q] = 0u - (b & 1u);
     }
     uint32_t found[K], top[N1];
-#pragma unroll
-    for (int c = 0; c < K; ++c) found[c] = 0u;
-#pragma unroll
-    for (int c = 0; c < N1; ++c) top[c] = 0u;
     const uint4* sp = reinterpret_cast<const uint4*>(svt);
+    const uint32_t ub = (12u + 8u * myb) >> 2;   // the lane's thresholds, in uint4 units
     for (uint32_t g = 0; g < nv; ++g) {
-        uint32_t x[20];
+        const uint32_t at = g * (stride >> 2);
+        uint32_t x[12], uu[8];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            const uint4 v = sp[g * (kDenseWords / 4) + i];
+        for (int i = 0; i < 3; ++i) {
+            const uint4 v = sp[at + i];
             x[4 * i] = v.x;
             x[4 * i + 1] = v.y;
             x[4 * i + 2] = v.z;
             x[4 * i + 3] = v.w;
         }
-        // words: 0..6 U_k; 7..12 high plane of positions Q..Q+5; 13..18 low.
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const uint4 v = sp[at + ub + i];
+            uu[4 * i] = v.x;
+            uu[4 * i + 1] = v.y;
+            uu[4 * i + 2] = v.z;
+            uu[4 * i + 3] = v.w;
+        }
+        // x: 0..5 high plane of positions Q..Q+5, 6..11 low plane.
         uint32_t m[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) m[q] = bop3<kOrXor>(x[7 + q] ^ ch[q], x[13 + q], cl[q]);
+        for (int q = 0; q < 3; ++q) m[q] = bop3<kOrXor>(x[q] ^ ch[q], x[6 + q], cl[q]);
         uint32_t v1[6], v2[5], t[4];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) v1[k] = bop3<kMux>(m[0], x[k + 1], x[k]);
+        for (int k = 0; k < 6; ++k) v1[k] = bop3<kMux>(m[0], uu[k + 1], uu[k]);
 #pragma unroll
         for (int k = 0; k < 5; ++k) v2[k] = bop3<kMux>(m[1], v1[k + 1], v1[k]);
 #pragma unroll
@@ -690,13 +723,16 @@ __device__ __forceinline__ uint64_t scan_filtered(uint32_t nv, const uint32_t* _
         uint32_t sv[S][4];
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            const uint32_t h = x[10 + q], lo = x[16 + q];
+            const uint32_t h = x[3 + q], lo = x[9 + q];
             sv[q][0] = bop3<0xFC>(h, lo, 0u);   // h | lo
             sv[q][1] = bop3<0xF3>(h, lo, 0u);   // h | ~lo
             sv[q][2] = bop3<0xCF>(h, lo, 0u);   // ~h | lo
             sv[q][3] = bop3<0x3F>(h, lo, 0u);   // ~(h & lo)
         }
-        select_accumulate<S>(t, sv, found, top);
+        if (g == 0)
+            select_accumulate<S, true>(t, sv, found, top);
+        else
+            select_accumulate<S>(t, sv, found, top);
     }
     return group_pass<S>(found, top) & alive;
 }
@@ -1010,58 +1046,59 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         Mask pass;
         if constexpr (S == 3) {
             // Blocks of 64 consecutive groups among the live lanes, each
-            // given `groups` table lanes; the shared-prefix scan applies when
-            // they all fit (one block for an aligned stage-0 batch).
-            // (Counted first with wave-uniform values only, then the
-            // per-lane block data inside the branch that uses it: computed
-            // ahead of the branch, it cost the general scan registers.)
-            // One block: the window filter first (dense window groups in
-            // svt; kNoFit when too many windows pass it).
-            uint32_t nv = kNoFit;
-            if (filter && P >= 3u && groups <= 64u) {
-                const uint64_t live = ballot(alive != 0);
-                if (live) {
-                    const uint32_t v0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(
-                        static_cast<int>(prefix >> 6), static_cast<int>(__builtin_ctzll(live))));
-                    if (ballot(alive != 0 && (prefix >> 6) != v0) == 0)
-                        nv = filter_windows_any(P, W + s * row, groups, v0, d, svt);
-                }
-            }
-            bool blocks_fit = false;
-            if (nv == kNoFit && P >= 3u && groups * 12u <= PMS_SVT_WORDS) {
+            // given `groups` table lanes; when they all fit, the window filter
+            // (dense window groups of the windows that can pass) or the
+            // shared-prefix scan of every window.  (Counted first with
+            // wave-uniform values only, then the per-lane block data inside
+            // the branch that uses it: computed ahead of the branch, it cost
+            // the general scan registers.)
+            uint32_t nblk = 0;
+            if (P >= 3u && groups <= 64u) {
                 const uint32_t kmax = 64u / groups;
                 uint64_t todo = ballot(alive != 0);
-                for (uint32_t k = 0; todo != 0 && k < kmax; ++k) {
+                for (; todo != 0 && nblk <= kmax; ++nblk) {
                     const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
                         static_cast<int>(prefix >> 6), static_cast<int>(__builtin_ctzll(todo))));
                     todo &= ~ballot((prefix >> 6) == v);
                 }
-                blocks_fit = todo == 0;
+                if (todo != 0 || nblk > kmax) nblk = 0;
             }
-            if (nv != kNoFit) {
-                pass = scan_filtered(nv, svt, prefix & 63u, alive);
-                ++filtered;
-                filtered_groups += nv;
-            } else if (blocks_fit) {
-                const uint32_t kmax = 64u / groups;
+            const bool use_filter = filter && nblk != 0 && nblk <= kFilterBlocks;
+            const bool use_shared = nblk != 0 && groups * 12u <= PMS_SVT_WORDS;
+            bool done = false;
+            if (use_filter || use_shared) {
                 const uint32_t hi = prefix >> 6;
-                uint32_t kv = 0, tj = 64u, src = 0;
+                uint32_t kv = 0, tj = 64u, myb = 0;
                 uint64_t todo = ballot(alive != 0);
-                for (uint32_t k = 0; todo != 0 && k < kmax; ++k) {
+                for (uint32_t k = 0; todo != 0; ++k) {
                     const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
                         static_cast<int>(hi), static_cast<int>(__builtin_ctzll(todo))));
                     const bool mine = hi == v;
                     todo &= ~ballot(mine);
                     const uint32_t b = k * groups;
-                    if (mine) src = b;
+                    if (mine) myb = k;
                     if (lane - b < groups) {
                         kv = v;
                         tj = lane - b;
                     }
                 }
-                pass = scan_group_shared_any(P, W + s * row, groups, kv, tj, src, prefix & 63u, d,
-                                             alive, svt);
-            } else {
+                if (use_filter) {
+                    const uint32_t nv =
+                        filter_windows_any(P, W + s * row, groups, nblk, kv, tj, d, svt);
+                    if (nv != kNoFit) {
+                        pass = scan_filtered(nv, 12u + 8u * nblk, myb, svt, prefix & 63u, alive);
+                        ++filtered;
+                        filtered_groups += nv;
+                        done = true;
+                    }
+                }
+                if (!done && use_shared) {
+                    pass = scan_group_shared_any(P, W + s * row, groups, kv, tj, myb * groups,
+                                                 prefix & 63u, d, alive, svt);
+                    done = true;
+                }
+            }
+            if (!done) {
                 pass = scan_group_any<S>(P, W + s * row, groups, prefix, d, alive);
             }
         } else {

@@ -2,16 +2,19 @@
 exactly (motif sets and the enhanced rule's visit counts), with the filter on
 and off.
 
-A group batch whose live lanes all lie in one block of 64 consecutive groups
-(every fresh stage-0 batch) keeps only the windows within d of the block's
-shared first l-6 bases, re-sliced into dense 32-window groups of 20 LDS words
-each (at most 25 of them); rows of more than 64 window groups, and batches
-that would need more than 25 dense groups, scan every window.  The cases
-straddle those limits (G = 1, 2, 25/26, 31, 63/64/65 window groups per row),
-include shapes where most windows pass (l = 6: no shared base, so every
-window passes and the table overflows from 26 window groups on) and where
-almost none pass ((16,2)), and reach deeper stages.  The filtered batches and
-dense groups the kernel counts show which path ran.
+A group batch whose live lanes lie in at most four blocks of 64 consecutive
+groups (every fresh stage-0 batch is one block; deeper batches often span
+two or three) keeps only the windows within d of some block's shared first
+l-6 bases, re-sliced into dense 32-window groups of 12 + 8 x blocks LDS
+words each beside a 64-entry list of the windows that pass (at most 22
+dense groups for one block); rows of more than 64 window groups, batches
+over more blocks, and batches that would need more dense groups than fit
+scan every window.  The cases straddle those limits (G = 1, 2, 19, 22/23,
+31, 63/64/65 window groups per row), include shapes where most windows pass
+(l = 6: no shared base, so every window passes and the table overflows from
+23 window groups on) and where almost none pass ((16,2)), and reach deeper
+stages.  The filtered batches and dense groups the kernel counts show which
+path ran.
 """
 import numpy as np
 import pytest
@@ -51,7 +54,7 @@ def solve_both(nat, inst, l, d):
 
 
 @pytest.mark.parametrize("l,d,G,ragged", [(9, 2, 1, 0), (9, 2, 2, 5), (11, 3, 19, 3),
-                                          (10, 2, 25, 0), (10, 2, 26, 0), (10, 2, 31, 1),
+                                          (10, 2, 22, 0), (10, 2, 23, 0), (10, 2, 31, 1),
                                           (10, 2, 63, 0), (10, 2, 64, 0), (10, 2, 65, 0)])
 def test_filter_window_group_counts(nat, l, d, G, ragged):
     n = 8
@@ -75,9 +78,9 @@ def test_filter_window_group_counts(nat, l, d, G, ragged):
         assert s_on["filtered_batches"] == 0
 
 
-@pytest.mark.parametrize("G", [25, 26, 40])
+@pytest.mark.parametrize("G", [22, 23, 40])
 def test_filter_every_window_passes(nat, G):
-    """l = 6: no shared base, so U_0 is set for every window; up to 25 dense
+    """l = 6: no shared base, so U_0 is set for every window; up to 22 dense
     groups the filter path runs (with nothing to skip), beyond it the batch
     falls back to the unfiltered scans."""
     l, d, n = 6, 1, 5
@@ -88,7 +91,7 @@ def test_filter_every_window_passes(nat, G):
     (on, s_on), (off, _) = solve_both(nat, inst, l, d)
     assert np.array_equal(on, want) and np.array_equal(off, want)
     assert s_on["seq_visits"] == visits
-    if G <= 25:
+    if G <= 22:
         assert s_on["filtered_batches"] > 0
     else:
         assert s_on["filtered_batches"] == 0
