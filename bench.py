@@ -32,6 +32,13 @@ VALU_INT32_PEAK = CUS * LANES_PER_CU * CLOCK_HZ          # lane-ops/s
 # Per-lane kernel: VALU instructions per window compare in its inner loop
 # (v_xor_b32, v_or_b32_sdwa, v_bcnt_u32_b32 and half of a v_min3_u32).
 LANE_OPS_PER_COMPARE = 3.5
+# Algorithmic operations per window compare: the method's compare without
+# skipping any window, in its cheapest form here -- the 64-candidate
+# kernel's shared-prefix scan, whose loop takes 147 VALU instructions per 32
+# windows x 64 candidates at l = 15 in the ISA of this build (the loop with 7
+# ds_bpermute and 3 ds_read_b128 per iteration).  W_skip x this / kernel time
+# is the algorithmic work rate reported as the roofline's `achieved`.
+ALG_OPS_PER_COMPARE = 147.0 / (32 * 64)
 KERNELS = {1: ("pms_search_kernel", "pms_kernels.hip"),
            2: ("pms_search_group_kernel", "pms_group.hip"),
            3: ("pms_search_group64_kernel", "pms_group.hip")}
@@ -53,6 +60,13 @@ def parse():
                     help="search kernel variant")
     ap.add_argument("--filter", default="on", choices=["on", "off"],
                     help="window filter of the 64-candidate kernel (off: every window scanned)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="leave out the batched leg (256 instances in one launch) of the default line")
+    ap.add_argument("--no-plain-filter-off", action="store_true",
+                    help="leave out the unfiltered comparison run of the default line")
+    ap.add_argument("--skip-host-level", action="store_true",
+                    help="leave out the host-level pms_solve timings (profiling runs: then the "
+                         "timed steps are the only search launches)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -149,8 +163,9 @@ def bench_plain(args):
     import fmgen
     from paper_1403_1313_amd import native as nat
 
-    nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant],
-                   filter=nat.FILTER_ON if args.filter == "on" else nat.FILTER_OFF)
+    variant = {"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant]
+    filt = nat.FILTER_ON if args.filter == "on" else nat.FILTER_OFF
+    nat.set_config(variant=variant, filter=filt)
     shape = fmgen.PLAIN[args.config]
     inst = fmgen.gen_fm(seed=args.seed, **shape)
     l, d, n, t = inst.l, inst.d, inst.n, inst.t
@@ -176,50 +191,47 @@ def bench_plain(args):
         codes = np.sort(got.numpy().view(np.uint32))
         return codes, nat.last_stats()
 
-    for _ in range(args.warmup):
-        codes, st = step()
-    torch.cuda.synchronize()
-    kernel_ms, windows_ms, step_wall = [], [], []
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    w0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        codes, st = step()
-        step_wall.append(time.perf_counter() - s0)
-        kernel_ms.append(st["kernel_ms"])
-        windows_ms.append(st["windows_ms"])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_total = e0.elapsed_time(e1)
+    def timed(steps, warmup):
+        """(codes, stats, per-step kernel ms, windows ms, step wall s, total wall s, event ms)."""
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        kernel_ms, windows_ms, step_wall = [], [], []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        w0 = time.perf_counter()
+        codes = st = None
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            codes, st = step()
+            step_wall.append(time.perf_counter() - s0)
+            kernel_ms.append(st["kernel_ms"])
+            windows_ms.append(st["windows_ms"])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return codes, st, kernel_ms, windows_ms, step_wall, time.perf_counter() - w0, e0.elapsed_time(e1)
+
+    codes, st, kernel_ms, windows_ms, step_wall, wall, ms_total = timed(args.steps, args.warmup)
     ms_step = ms_total / args.steps
     cands = 4 ** l
     k_ms = float(np.mean(kernel_ms))
     wc = st["window_compares"]
     kname, ksrc = KERNELS[st["variant"]]
     rec, fresh = load_counters(args.counters, f"{kname}/{args.config}", ksrc)
-    if st["variant"] == 1:
-        opc, opc_src = LANE_OPS_PER_COMPARE, "inner-loop ISA: 56 VALU per 16 windows"
-    elif rec:
-        # executed VALU lane-operations per algorithmic compare (SQ_INSTS_VALU x 64 / W)
-        opc = rec["valu_insts_per_launch"] * 64 / rec["window_compares"]
-        opc_src = "SQ_INSTS_VALU x 64 / window compares" + ("" if fresh else " (kernel changed since)")
+    # Algorithmic work of the launch: W_skip window compares at the cost of
+    # the method's compare loop with no window skipped (the per-lane kernel:
+    # its own loop).
+    alg_opc = LANE_OPS_PER_COMPARE if st["variant"] == 1 else ALG_OPS_PER_COMPARE
+    achieved = wc * alg_opc / (k_ms * 1e-3)
+    # Executed VALU work from the counter run of this kernel source.
+    if rec and fresh:
+        exec_opc = rec["valu_insts_per_launch"] * 64 / rec["window_compares"]
+        exec_src = "SQ_INSTS_VALU x 64 / window compares (" + rec.get("profile", "profiles/") + ")"
+    elif st["variant"] == 1:
+        exec_opc, exec_src = LANE_OPS_PER_COMPARE, "inner-loop ISA: 56 VALU per 16 windows"
     else:
-        opc, opc_src = None, "no counter run for this kernel"
-    achieved = wc * opc / (k_ms * 1e-3) if opc else None
-
-    # The host-level call on the same instance (host rows in, sorted motifs
-    # out: validation, upload, both kernels, copy-back and sort).
-    host_walls, host_prep, host_finish = [], [], []
-    for _ in range(5):
-        h0 = time.perf_counter()
-        nat.solve(inst.seqs, l, d)
-        host_walls.append(time.perf_counter() - h0)
-        hs = nat.last_stats()
-        host_prep.append(hs["host_prep_ms"])
-        host_finish.append(hs["host_finish_ms"])
+        exec_opc, exec_src = None, ("no counter run for this kernel source" if not rec
+                                    else "kernel changed since the counter run")
 
     parity = None
     gpath = os.path.join(ROOT, "tests", "golden", f"{args.config}.json")
@@ -268,23 +280,64 @@ def bench_plain(args):
         "motifs": int(codes.size),
         "parity_vs_golden": parity,
         "launch": {"grid": st["grid"], "wg_waves": st["wg_waves"], "chunk": st["chunk"]},
-        "host_level_pms_solve_ms": {"median": float(np.median(host_walls)) * 1e3,
-                                    "min": float(np.min(host_walls)) * 1e3,
-                                    "prep_median": float(np.median(host_prep)),
-                                    "finish_median": float(np.median(host_finish))},
         "roofline": {
             "bound": "alu",
-            "achieved": achieved / 1e12 if achieved else None,
+            "achieved": achieved / 1e12,
             "peak": VALU_INT32_PEAK / 1e12,
             "unit": "Tops/s",
-            "frac": achieved / VALU_INT32_PEAK if achieved else None,
+            "frac": achieved / VALU_INT32_PEAK,
             "traffic": traffic,
             "kernel": kname,
-            "ops_per_compare": opc,
-            "ops_per_compare_source": opc_src,
+            "ops_per_compare": alg_opc,
+            "ops_per_compare_source": ("per-lane kernel loop ISA" if st["variant"] == 1 else
+                                       "shared-prefix scan loop ISA: 147 VALU per 32 windows x 64 "
+                                       "candidates, no window skipped"),
+            "frac_valu_issued": (wc * exec_opc / (k_ms * 1e-3) / VALU_INT32_PEAK
+                                 if exec_opc else None),
+            "executed_ops_per_compare": exec_opc,
+            "executed_ops_source": exec_src,
         },
         "cpu_baseline": None,
     }
+    if not args.skip_host_level:
+        # The host-level call on the same instance (host rows in, sorted motifs
+        # out: validation, upload, both kernels, copy-back and sort).
+        host_walls, host_prep, host_finish = [], [], []
+        for _ in range(5):
+            h0 = time.perf_counter()
+            nat.solve(inst.seqs, l, d)
+            host_walls.append(time.perf_counter() - h0)
+            hs = nat.last_stats()
+            host_prep.append(hs["host_prep_ms"])
+            host_finish.append(hs["host_finish_ms"])
+        line["host_level_pms_solve_ms"] = {"median": float(np.median(host_walls)) * 1e3,
+                                           "min": float(np.min(host_walls)) * 1e3,
+                                           "prep_median": float(np.median(host_prep)),
+                                           "finish_median": float(np.median(host_finish))}
+    if not args.no_plain_filter_off and filt == nat.FILTER_ON and st["variant"] == 3:
+        # The same steps with every window scanned (the unfiltered sweep of the
+        # method's enhanced rule), reported apart from the filtered path.
+        nat.set_config(variant=variant, filter=nat.FILTER_OFF)
+        codes0, st0, kms0, _, _, _, mst0 = timed(args.steps, max(1, args.warmup))
+        k0 = float(np.mean(kms0))
+        line["unfiltered"] = {
+            "ms_per_step": mst0 / args.steps, "kernel_ms": k0,
+            "candidates_per_s": cands / (mst0 / args.steps * 1e-3),
+            "roofline_frac": wc * ALG_OPS_PER_COMPARE / (k0 * 1e-3) / VALU_INT32_PEAK,
+            "same_motifs": bool(np.array_equal(codes0, codes)),
+            "same_visits": st0["seq_visits"] == st["seq_visits"],
+            "filter_speedup": k0 / k_ms}
+        nat.set_config(variant=variant, filter=filt)
+    if not args.no_batched:
+        from paper_1403_1313_amd import benchmarks
+        bl = benchmarks.bench_batched(args, emit=False)
+        line["batched"] = {k: bl[k] for k in (
+            "value", "unit", "ms_per_step", "instance_latency_ms_p50", "instance_latency_ms_p99",
+            "speedup_vs_one_per_launch", "one_per_launch", "parity_vs_golden", "graph_ms_median",
+            "eager", "autotuned", "candidates_per_s", "window_compares_per_s",
+            "filtered_batches", "filtered_dense_groups")}
+        line["batched"]["workload"] = bl["config"]["workload"]
+        nat.set_config(variant=variant, filter=filt)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst.seqs, l, d, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -336,7 +389,8 @@ def main():
         return bench_copy(args)
     if args.mode == "batched":
         from paper_1403_1313_amd import benchmarks
-        return benchmarks.bench_batched(args)
+        benchmarks.bench_batched(args)
+        return 0
     if args.mode == "ex":
         from paper_1403_1313_amd import benchmarks
         return benchmarks.bench_ex(args)

@@ -31,7 +31,10 @@ def _sha(codes):
     return hashlib.sha256(np.ascontiguousarray(codes, dtype="<u4").tobytes()).hexdigest()
 
 
-def bench_batched(args):
+def bench_batched(args, emit=True):
+    """The batched workload: 256 instances in one persistent launch replayed
+    from a HIP graph, autotuned, against one pms_solve per instance.  Prints
+    the line (emit) and returns it."""
     import fmgen
     from . import native as nat
 
@@ -46,7 +49,8 @@ def bench_batched(args):
     except OSError:
         import tempfile
         cache = os.path.join(tempfile.gettempdir(), "paper_1403_1313_amd_autotune.json")
-    nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant])
+    nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant],
+                   filter=nat.FILTER_OFF if getattr(args, "filter", "on") == "off" else nat.FILTER_ON)
     t0 = time.perf_counter()
     tuned = nat.autotune(20, 650, 13, 4, cache)
     tune_s = time.perf_counter() - t0
@@ -132,9 +136,14 @@ def bench_batched(args):
                            "latency_ms_p99": _pct(per_launch_ms, 99)},
         "speedup_vs_one_per_launch": plain_s / wall,
         "parity_vs_golden": parity,
+        "filtered_batches": eager["filtered_batches"],
+        "filtered_dense_groups": eager["filtered_groups"],
+        "batches": eager["batches"], "single_batches": eager["single_batches"],
     }
-    print(json.dumps(line), flush=True)
-    return 0
+    nat.set_config(reset=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 def bench_serving(args):

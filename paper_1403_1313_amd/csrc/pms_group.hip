@@ -646,6 +646,28 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
     return nv;
 }
 
+// The most blocks (up to kFilterBlocks) over which the window filter is
+// expected to keep at most half of the windows, so that it pays for its
+// re-slicing: a random window is within d of a block's Q shared bases with
+// probability p = sum_{k<=d} C(Q,k) 3^k / 4^Q, and of some block's of nb with
+// 1 - (1-p)^nb.  0 when even one block keeps more than half.
+__device__ __forceinline__ uint32_t filter_block_limit(uint32_t Q, int d) {
+    double ball = 0.0, c = 1.0, p3 = 1.0;
+    for (uint32_t k = 0; k <= Q && static_cast<int>(k) <= d; ++k) {
+        ball += c * p3;
+        c = c * static_cast<double>(Q - k) / static_cast<double>(k + 1);
+        p3 *= 3.0;
+    }
+    const double keep = 1.0 - ball / ldexp(1.0, 2 * static_cast<int>(Q));
+    double r = 1.0;
+    uint32_t nb = 0;
+    for (uint32_t b = 1; b <= kFilterBlocks; ++b) {
+        r *= keep;
+        if (r >= 0.5) nb = b;
+    }
+    return nb;
+}
+
 // Dispatch on P (wave-uniform, 3..13).
 __device__ __forceinline__ uint32_t filter_windows_any(uint32_t P, cu32* W, uint32_t groups,
                                                        uint32_t nb, uint32_t kv, uint32_t tj,
@@ -851,6 +873,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     uint32_t* out = nullptr;
     uint64_t cap = 0;
     uint32_t n = 0, row = 0, groups = 0, P = 0;
+    uint32_t fmax = 0;    // window filter: most blocks per batch (0: off)
     int d = 0;
 
     for (;;) {
@@ -963,6 +986,8 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 P = static_cast<uint32_t>(in.l) - S;
                 groups = row / (2u * (P + S));
                 d = in.d;
+                if constexpr (S == 3)
+                    fmax = filter && P >= 3u ? uni(filter_block_limit(P - 3u, d)) : 0u;
                 pending = 1;
                 next = wi.begin >> (2 * S);
                 end = (wi.begin + wi.len) >> (2 * S);
@@ -1063,7 +1088,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 }
                 if (todo != 0 || nblk > kmax) nblk = 0;
             }
-            const bool use_filter = filter && nblk != 0 && nblk <= kFilterBlocks;
+            const bool use_filter = nblk != 0 && nblk <= fmax;
             const bool use_shared = nblk != 0 && groups * 12u <= PMS_SVT_WORDS;
             bool done = false;
             if (use_filter || use_shared) {
