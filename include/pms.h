@@ -51,7 +51,11 @@ enum pms_status {
 #define PMS_MAX_T (1 << 17)
 
 /*
- * pms_solve -- one instance, host buffers in and out, synchronous.
+ * pms_solve -- one instance, host buffers in and out, synchronous.  The
+ * problem of Section I.A solved by the enhanced brute force of Section III.A
+ * (every l-mer a candidate; a candidate is dropped at the first sequence
+ * without a window within d), the candidate numbers split into index ranges
+ * as in Section IV.A.
  *
  *   seqs        n pointers, each to at least t bytes of A/C/G/T (either
  *               case); no terminator needed.  Read only; nothing retained.
@@ -127,7 +131,9 @@ typedef struct {
 
 /*
  * pms_solve_many -- many independent instances of uneven (l, d, n, t) in one
- * persistent launch (replayed from a captured HIP graph when the batch has
+ * persistent launch, each solved by the method of Section III.A as in
+ * pms_solve (the paper runs one instance per program run; sharing one launch
+ * among many is this library's) (replayed from a captured HIP graph when the batch has
  * the same layout as the previous call).  Same per-instance semantics as
  * pms_solve.  An invalid instance gets PMS_ERR_INVALID and does not stop the
  * others.  Returns PMS_OK when every instance is OK, else the first non-OK
@@ -135,7 +141,9 @@ typedef struct {
  */
 int pms_solve_many(const pms_instance* inst, int32_t count, pms_result* results);
 
-/* Writes the l characters of motif `code` to out (no terminator). */
+/* Writes the l characters of motif `code` to out (no terminator); the code's
+ * base order A < C < G < T is the dictionary order of the strings (the paper
+ * fixes no encoding). */
 void pms_decode(uint32_t code, int32_t l, char* out);
 
 /* Static text for a status code. */
@@ -206,12 +214,15 @@ typedef struct {
 } pms_config;
 
 /* Sets the configuration used by later calls that pass no configuration
- * (NULL restores the defaults).  PMS_ERR_INVALID for out-of-range fields. */
+ * (NULL restores the defaults).  PMS_ERR_INVALID for out-of-range fields.
+ * The launch shape is this library's; the paper's one knob is the number of
+ * threads that share the index ranges (Section IV.A). */
 int pms_set_config(const pms_config* cfg);
 int pms_get_config(pms_config* cfg);
 
 /*
- * pms_autotune -- times the candidate-chunk x workgroup-shape grid on one
+ * pms_autotune -- (launch shape, not part of the paper's method) times the
+ * candidate-chunk x workgroup-shape grid on one
  * instance shape (FM synthetic data drawn inside the library from a fixed
  * seed) and makes the fastest the current configuration.  The result is
  * cached in the JSON file named by cache_path (or $PMS_AUTOTUNE_CACHE when
@@ -221,7 +232,9 @@ int pms_get_config(pms_config* cfg);
 int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_path,
                  pms_config* best);
 
-/* Counters of the last solve on this device.  After a device-level call
+/* Counters of the last solve on this device.  seq_visits counts the
+ * (candidate, sequence) scans that the enhanced rule of Section III.A makes,
+ * the method's own work; the others describe this library's launches.  After a device-level call
  * (pms_solve_dev, pms_step_launch) pms_last_stats waits for that call's
  * kernels and for its counters, which pms_solve_dev copies to pinned host
  * memory on the caller's stream right after the search. */
@@ -304,10 +317,11 @@ int pms_valu_probe(int op, int32_t waves_per_simd, int32_t iters, pms_probe_resu
 int32_t pms_window_stride(int32_t t, int32_t l, int32_t layout);
 
 /*
- * pms_build_windows -- steps a1+a2: encodes n rows of t bytes (row-major at
- * dev_seqs, device memory) into 2-bit codes, stages each row in LDS, and
- * writes every window of length l to dev_windows[n][pms_window_stride(t, l,
- * layout)].  PLANES: window j is (high-bit plane of base p in bit 16+l-1-p,
+ * pms_build_windows -- steps a1+a2, the windows of every sequence that
+ * Section III.A extracts before the comparisons: encodes n rows of t bytes
+ * (row-major at dev_seqs, device memory) into 2-bit codes, stages each row
+ * in LDS, and writes every window of length l to
+ * dev_windows[n][pms_window_stride(t, l, layout)].  PLANES: window j is (high-bit plane of base p in bit 16+l-1-p,
  * low-bit plane in bit l-1-p).  BITSLICED: see pms_layout.  Window slots past
  * t-l+1 repeat window 0.  Bytes that are not A/C/G/T (either case) set
  * *dev_bad (device uint32) to 1; dev_bad may be NULL.  Asynchronous on
@@ -359,7 +373,10 @@ typedef struct {
 } pms_dev_counters;
 
 /*
- * pms_step_launch -- steps a3-a6: one persistent search launch over the
+ * pms_step_launch -- steps a3-a6 of the sweep of Section III.A (candidates
+ * generated from their index numbers, compared window by window, dropped at
+ * the first sequence without a match, survivors output) over caller-built
+ * index ranges as in Section IV.A: one persistent search launch over the
  * work items dev_work[0 .. n_work).  Each instance's survivors are appended
  * (unsorted, as motif codes) to its `out`; its state counts them.  cfg may be
  * NULL (current configuration); its variant selects the kernel and so the
@@ -374,7 +391,8 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
                     const pms_config* cfg, void* stream);
 
 /*
- * pms_solve_dev -- the whole device part of one solve on the caller's stream:
+ * pms_solve_dev -- the whole device part of one solve (Section III.A's method
+ * on device buffers) on the caller's stream:
  * builds windows, lays out work items, and runs the search.  dev_seqs holds
  * n*t bytes row-major on the device.  Motif codes are appended, unsorted, to
  * dev_out (capacity `capacity`); *dev_count (device uint64) receives |M|
