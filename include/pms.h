@@ -146,6 +146,14 @@ int pms_solve_many(const pms_instance* inst, int32_t count, pms_result* results)
  * fixes no encoding). */
 void pms_decode(uint32_t code, int32_t l, char* out);
 
+/* Sorts `count` motif codes of length l ascending in place (step a7 for
+ * codes a device-level caller copied back unsorted; a least-significant-digit
+ * radix sort over the codes' 2l bits above 4096 codes).  PMS_ERR_INVALID for
+ * l out of range, NULL codes with count > 0 or a code with bits above 2l
+ * (nothing is reordered then); PMS_ERR_DEVICE if two codes are equal (a
+ * motif set has none; the codes are sorted all the same). */
+int pms_sort_codes(uint32_t* codes, uint64_t count, int32_t l);
+
 /* Static text for a status code. */
 const char* pms_status_string(int status);
 

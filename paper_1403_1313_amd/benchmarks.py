@@ -180,19 +180,32 @@ def bench_serving(args):
             stats = dict(srv.stats)
             stats["compares_per_s_estimate"] = srv.rate
         lat = [r.latency_s * 1e3 for r in results]
+        # Where the time of the slowest requests goes (host clock, ms).
+        worst = sorted(results, key=lambda r: r.latency_s)[-max(1, len(results) // 100):]
+        parts = {"admit": [1e3 * (r.admitted - r.arrival) for r in worst],
+                 "to_first_step": [1e3 * (r.launched - r.admitted) for r in worst],
+                 "steps": [1e3 * (r.retired - r.launched) for r in worst],
+                 "finish": [1e3 * (r.finished - r.retired) for r in worst],
+                 "step_count": [r.steps for r in worst]}
         # the same arrivals served one instance per launch, first come first served
         t1 = time.perf_counter()
-        fifo_lat = []
+        fifo_lat, fifo_codes = [], []
         for t_arr, inst in reqs:
             now = time.perf_counter() - t1
             if t_arr > now:
                 time.sleep(t_arr - now)
-            st, cnt, _ = nat.solve_raw(inst.seqs, inst.l, inst.d, capacity=1 << 21)
+            st, cnt, codes = nat.solve_raw(inst.seqs, inst.l, inst.d, capacity=1 << 21)
             fifo_lat.append((time.perf_counter() - t1 - t_arr) * 1e3)
+            fifo_codes.append((st, cnt, codes))
         fifo_span = time.perf_counter() - t1
+        # Every served result against the same request solved alone by pms_solve.
+        same = sum(1 for r, (st, cnt, codes) in zip(results, fifo_codes)
+                   if st == nat.PMS_OK and r.count == cnt and np.array_equal(r.motifs, codes))
         out.append({"rate": rate, "requests": count, "solves_per_s": count / span,
                     "latency_ms_p50": _pct(lat, 50), "latency_ms_p99": _pct(lat, 99),
                     "server_stats": stats,
+                    "slowest_1pct_mean_ms": {k: float(np.mean(v)) for k, v in parts.items()},
+                    "parity_vs_solo": {"ok": same == count, "requests_equal": same},
                     "one_per_launch_fifo": {"solves_per_s": count / fifo_span,
                                             "latency_ms_p50": _pct(fifo_lat, 50),
                                             "latency_ms_p99": _pct(fifo_lat, 99)}})

@@ -1013,6 +1013,20 @@ const char* pms_status_string(int status) {
 
 const char* pms_last_error(void) { return g_last_error.c_str(); }
 
+int pms_sort_codes(uint32_t* codes, uint64_t count, int32_t l) {
+    g_last_error.clear();
+    if (l < 1 || l > PMS_MAX_L) return fail(PMS_ERR_INVALID, "l out of range [1, 16]");
+    if (count > 0 && !codes) return fail(PMS_ERR_INVALID, "codes is NULL");
+    const uint32_t mask = l == 16 ? ~0u : ((1u << (2 * l)) - 1u);
+    for (uint64_t i = 0; i < count; ++i)
+        if (codes[i] & ~mask) return fail(PMS_ERR_INVALID, "a code has bits above 2l");
+    std::vector<uint32_t> tmp;
+    sort_codes(codes, static_cast<size_t>(count), 2 * l, tmp);
+    for (uint64_t i = 1; i < count; ++i)
+        if (codes[i] == codes[i - 1]) return fail(PMS_ERR_DEVICE, "duplicate motif code");
+    return PMS_OK;
+}
+
 void pms_decode(uint32_t code, int32_t l, char* out) {
     if (!out || l < 1 || l > PMS_MAX_L) return;
     for (int32_t p = 0; p < l; ++p) out[p] = "ACGT"[(code >> (2 * (l - 1 - p))) & 3u];

@@ -22,7 +22,8 @@ PMS_MAX_L, PMS_MAX_N, PMS_MAX_T = 16, 64, 1 << 17
 SYMBOLS = ["pms_solve", "pms_solve_ex", "pms_solve_intersect", "pms_solve_many", "pms_decode", "pms_status_string", "pms_last_error",
            "pms_set_config", "pms_get_config", "pms_autotune", "pms_last_stats",
            "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev",
-           "pms_valu_probe", "pms_solve_dev_noalloc", "pms_shutdown"]
+           "pms_valu_probe", "pms_solve_dev_noalloc", "pms_shutdown",
+           "pms_sort_codes"]
 PROBE_OPS = {"xor": 0, "bcnt": 1, "min3": 2, "or_sdwa": 3, "add": 4, "fma_f32": 5, "xor_vv": 6,
              "compare": 7, "mov_s": 8, "mov64_s": 9}
 
@@ -158,6 +159,7 @@ def _load():
         "pms_valu_probe": ([ctypes.c_int, i32, i32, P(ProbeResult)], ctypes.c_int),
         "pms_solve_dev_noalloc": ([vp, i32, i32, i32, i32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
         "pms_shutdown": ([], ctypes.c_int),
+        "pms_sort_codes": ([u32p, ctypes.c_uint64, i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -345,6 +347,16 @@ def solve_many(instances: Sequence[Tuple[object, int, int]], capacities=None):
     take = np.minimum(counts, caps).astype(np.int64)
     motifs = [pool[offs[i]:offs[i] + take[i]].copy() for i in range(m)]
     return st, motifs, [res[i] for i in range(m)]
+
+
+def sort_codes(codes: np.ndarray, l: int) -> np.ndarray:
+    """pms_sort_codes: sorts a contiguous uint32 array of motif codes in place
+    and returns it."""
+    if codes.dtype != np.uint32 or not codes.flags["C_CONTIGUOUS"] or not codes.flags["WRITEABLE"]:
+        raise ValueError("codes must be a writable contiguous uint32 array")
+    _check(_lib.pms_sort_codes(codes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                               int(codes.size), int(l)))
+    return codes
 
 
 def decode(code: int, l: int) -> str:

@@ -35,7 +35,7 @@ from . import native as nat
 
 MAX_SLOTS = 1024
 ITEMS_UNTRACKED = 1 << 31  # serving does not use per-instance completion stamps
-EAGER_CODES = 1 << 16      # codes copied back right after a request's last step
+EAGER_CODES = 1 << 16      # least codes copied back right after a request's last step
 
 
 def _estimate(l: int, d: int, n: int, t: int):
@@ -58,6 +58,8 @@ class Result:
     steps: int
     reruns: int
     visits: int
+    launched: float = 0.0       # its first step launched
+    retired: float = 0.0        # its last step seen complete by the server
 
     @property
     def latency_s(self) -> float:
@@ -67,7 +69,8 @@ class Result:
 class _Req:
     __slots__ = ("rid", "seqs", "l", "d", "n", "t", "arrival", "future", "slot", "dev_seqs",
                  "dev_win", "dev_out", "cap", "bytes", "total", "cursor", "inflight", "steps",
-                 "reruns", "admitted", "cost_per_cand", "stride", "h_out", "failed")
+                 "reruns", "admitted", "cost_per_cand", "stride", "h_out", "failed",
+                 "launched", "retired", "est_m")
 
     def __init__(self, rid, seqs, l, d, arrival, future):
         self.rid = rid
@@ -80,6 +83,7 @@ class _Req:
         self.dev_seqs = self.dev_win = self.dev_out = None
         self.stride = nat.window_stride(self.t, l, nat.LAYOUT_BITSLICED) if l >= 2 else 0
         est_m, ev = _estimate(l, d, self.n, self.t)
+        self.est_m = est_m
         self.cap = int(min(4 ** l, 8 * est_m + 4096))
         self.cost_per_cand = (self.t - l + 1) * ev
         self.total = 4 ** l
@@ -90,10 +94,66 @@ class _Req:
         self.admitted = 0.0
         self.h_out = None   # pinned copy of the first codes, made right after the last step
         self.failed = False  # its future holds an error; slot kept until its steps retire
+        self.launched = 0.0
+        self.retired = 0.0
         self.bytes = self._bytes()
 
     def _bytes(self) -> int:
         return self.n * self.t + self.n * self.stride * 4 + self.cap * 4
+
+
+class _PinnedRing:
+    """Pinned staging slots reused in turn for host-to-device copies on one
+    stream: a slot is refilled only after the copy that last read it has run
+    (its event), so no request pays for a pinned allocation."""
+
+    def __init__(self, torch, slots: int, slot_bytes: int):
+        self.torch = torch
+        self.slot_bytes = slot_bytes
+        self.buf = torch.zeros(slots * slot_bytes, dtype=torch.uint8).pin_memory()
+        self.events = [None] * slots
+        self.next = 0
+
+    def stage(self, data: bytes):
+        """A pinned uint8 tensor holding `data` (None if it does not fit a slot)."""
+        if len(data) > self.slot_bytes:
+            return None, None
+        k = self.next
+        self.next = (k + 1) % len(self.events)
+        if self.events[k] is not None:
+            self.events[k].synchronize()
+        view = self.buf[k * self.slot_bytes:k * self.slot_bytes + len(data)]
+        view.numpy()[:] = np.frombuffer(data, dtype=np.uint8)
+        return view, k
+
+    def used(self, k, stream):
+        """Marks slot k as read by the copies just queued on `stream`."""
+        if k is None:
+            return
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        self.events[k] = ev
+
+
+class _PinnedPool:
+    """Pinned int32 buffers in power-of-two sizes, handed back once their
+    codes have been copied out, so finishing requests allocate no pinned
+    memory once the pool holds their sizes."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.free: Dict[int, List] = {}
+
+    def get(self, count: int):
+        size = 1 << max(12, (max(count, 1) - 1).bit_length())
+        lst = self.free.get(size)
+        if lst:
+            return lst.pop()
+        return self.torch.empty(size, dtype=self.torch.int32, pin_memory=True)
+
+    def put(self, buf):
+        if buf is not None:
+            self.free.setdefault(buf.numel(), []).append(buf)
 
 
 class _StepBuf:
@@ -170,6 +230,10 @@ class Server:
         self.d_insts = torch.zeros(MAX_SLOTS * 40, dtype=torch.uint8, device=self.dev)
         self.d_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8, device=self.dev)
         self.free_slots = list(range(MAX_SLOTS - 1, -1, -1))
+        # Pinned staging of uploaded rows and slot records (larger rows are
+        # pinned one by one).
+        self.ring = _PinnedRing(torch, 64, 64 << 10)
+        self.pool = _PinnedPool(torch)
         self.bufs = [_StepBuf(torch, self.dev, 2 * self.items_per_step) for _ in range(max_inflight)]
         self.idle_bufs = list(self.bufs)
         self.inflight: Deque[_StepBuf] = collections.deque()
@@ -283,6 +347,7 @@ class Server:
         self.free_slots.append(r.slot)
         self.mem_used -= r.bytes
         r.dev_seqs = r.dev_win = r.dev_out = None
+        self.pool.put(r.h_out)
         r.h_out = None
 
     def _launch_max_n(self, reqs) -> int:
@@ -292,9 +357,14 @@ class Server:
     def _upload(self, req: _Req):
         torch = self.torch
         req.slot = self.free_slots.pop()
+        raw = req.seqs.reshape(-1)
+        staged, k = self.ring.stage(raw.tobytes())
         with torch.cuda.stream(self.stream):
-            req.dev_seqs = torch.from_numpy(req.seqs.reshape(-1)).pin_memory().to(
-                self.dev, non_blocking=True)
+            req.dev_seqs = torch.empty(raw.size, dtype=torch.uint8, device=self.dev)
+            if staged is None:
+                staged = torch.from_numpy(raw).pin_memory()
+            req.dev_seqs.copy_(staged, non_blocking=True)
+            self.ring.used(k, self.stream)
             req.dev_win = torch.empty(req.n * req.stride, dtype=torch.int32, device=self.dev)
             req.dev_out = torch.empty(max(req.cap, 1), dtype=torch.int32, device=self.dev)
         nat.build_windows(req.dev_seqs, req.n, req.t, req.l, req.dev_win, None, stream=self.stream,
@@ -307,12 +377,11 @@ class Server:
         inst = nat.DevInstance(req.dev_win.data_ptr(), req.dev_out.data_ptr(), req.cap, req.n,
                                req.stride, req.l, req.d)
         st = nat.DevState(0, 0, 0, ITEMS_UNTRACKED, 0)
-        # A fresh pinned block per write; torch's pinned-memory cache keeps it
-        # alive until the asynchronous copy has run.
-        h = torch.frombuffer(bytearray(bytes(inst) + bytes(st)), dtype=torch.uint8).pin_memory()
+        h, k = self.ring.stage(bytes(inst) + bytes(st))
         with torch.cuda.stream(self.stream):
             self.d_insts[req.slot * 40:(req.slot + 1) * 40].copy_(h[:40], non_blocking=True)
             self.d_state[req.slot * 32:(req.slot + 1) * 32].copy_(h[40:72], non_blocking=True)
+            self.ring.used(k, self.stream)
 
     def _build_step(self, buf: _StepBuf) -> int:
         """Fills one step's work table up to the step budget.
@@ -442,15 +511,19 @@ class Server:
             # codes than were copied take the side-stream path.
             for r in buf.reqs:
                 if EAGER_CODES and r.cursor >= r.total:
-                    k = min(r.cap, EAGER_CODES)
-                    r.h_out = torch.empty(k, dtype=torch.int32, pin_memory=True)
-                    r.h_out.copy_(r.dev_out[:k], non_blocking=True)
+                    # Twice the expected motif count, at least EAGER_CODES.
+                    k = int(min(r.cap, max(EAGER_CODES, 2 * r.est_m)))
+                    self.pool.put(r.h_out)
+                    r.h_out = self.pool.get(k)
+                    r.h_out[:k].copy_(r.dev_out[:k], non_blocking=True)
             buf.done = torch.cuda.Event()
             buf.done.record(self.stream)
+        buf.launched = time.perf_counter()
         for r in buf.reqs:
             r.inflight += 1
             r.steps += 1
-        buf.launched = time.perf_counter()
+            if not r.launched:
+                r.launched = buf.launched
         self.inflight.append(buf)
         self.stats["steps"] += 1
         self.stats["items"] += n_items
@@ -491,6 +564,7 @@ class Server:
                     self._release(r)
                 continue
             if r.cursor >= r.total and r.inflight == 0:
+                r.retired = time.perf_counter()
                 self._finish(r, int(states[r.slot]["count"]), int(states[r.slot]["visits"]),
                              buf.event)
 
@@ -498,6 +572,7 @@ class Server:
         torch = self.torch
         if count > r.cap:
             # Reservation too small: run the request again with the exact size.
+            self.pool.put(r.h_out)
             r.h_out = None
             self.mem_used -= r.bytes
             r.cap = count
@@ -517,19 +592,20 @@ class Server:
         # refers to it); its buffers stay referenced until the copy is done.
         self.active.remove(r)
         self.free_slots.append(r.slot)
-        if r.h_out is not None and count <= r.h_out.numel():
+        eager_k = int(min(r.cap, max(EAGER_CODES, 2 * r.est_m)))
+        if r.h_out is not None and count <= eager_k:
             # The codes came back with the step (done_event has completed).
-            host = r.h_out[:count]
-            r.h_out = None
+            host, r.h_out = r.h_out, None
             self._deliver(r, host, count, visits)
             return
+        self.pool.put(r.h_out)
         r.h_out = None
         host = None
         if count:
-            host = torch.empty(count, dtype=torch.int32, pin_memory=True)
+            host = self.pool.get(count)
             self.copy_stream.wait_event(done_event)
             with torch.cuda.stream(self.copy_stream):
-                host.copy_(r.dev_out[:count], non_blocking=True)
+                host[:count].copy_(r.dev_out[:count], non_blocking=True)
         copied = torch.cuda.Event()
         copied.record(self.copy_stream)
         self.finishing.append((r, host, count, visits, copied))
@@ -548,9 +624,22 @@ class Server:
             self._deliver(r, host, count, visits)
 
     def _deliver(self, r: _Req, host, count: int, visits: int):
-        codes = np.sort(host.numpy().view(np.uint32)) if count else np.zeros(0, dtype=np.uint32)
+        """Sorts the codes copied to the pinned buffer `host` (handed back to
+        the pool) and completes the request."""
+        codes = np.zeros(0, dtype=np.uint32)
+        if count:
+            try:
+                codes = nat.sort_codes(host[:count].numpy().view(np.uint32).copy(), r.l)
+            except nat.PmsError as e:   # a repeated code: this request's result is wrong
+                self.pool.put(host)
+                self.mem_used -= r.bytes
+                r.dev_seqs = r.dev_win = r.dev_out = None
+                self.stats["failed"] += 1
+                r.future.set_exception(e)
+                return
+        self.pool.put(host)
         res = Result(codes, count, r.arrival, r.admitted, time.perf_counter(), r.steps,
-                     r.reruns, visits)
+                     r.reruns, visits, r.launched, r.retired)
         self.mem_used -= r.bytes
         r.dev_seqs = r.dev_win = r.dev_out = None
         self.stats["completed"] += 1
@@ -558,17 +647,18 @@ class Server:
 
     def _wait_step(self, buf: _StepBuf) -> bool:
         """Waits for a step to complete, up to the step timeout from its
-        launch (polling: an event wait could not be abandoned)."""
+        launch (polling: an event wait could not be abandoned).  Returns False
+        as soon as a request arrives, so that it is admitted and can join the
+        next step while this one runs."""
         deadline = buf.launched + self.step_timeout_s
-        spins = 0
         while not buf.done.query():
-            now = time.perf_counter()
-            if now > deadline:
+            if time.perf_counter() > deadline:
                 self.stats["step_timeouts"] += 1
                 raise StepTimeout(f"a search step has not completed {self.step_timeout_s:g} s "
                                   "after its launch")
-            spins += 1
-            time.sleep(0 if spins < 200 else 50e-6)
+            if self.waiting and self.free_slots:
+                return False
+            time.sleep(0)   # yield only: the step's end is seen within microseconds
         return True
 
     def _fail_all(self, exc: BaseException):

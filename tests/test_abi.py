@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 18
+    assert len(names) == 19
     assert sorted(nat.SYMBOLS) == names
     lib = ctypes.CDLL(nat.LIB_PATH)
     for name in names:
@@ -295,3 +295,20 @@ def test_shutdown_without_device_work():
     out = subprocess.run([__import__("sys").executable, "-c", code], cwd=ROOT, check=True,
                          capture_output=True, text=True).stdout.strip()
     assert out == "ok"
+
+
+def test_sort_codes():
+    """pms_sort_codes (host only): ascending order for both sort paths, and
+    its argument checks."""
+    rng = np.random.default_rng(5)
+    for l, k in [(1, 3), (8, 100), (11, 5000), (16, 20000), (13, 70000)]:
+        codes = rng.choice(4 ** l, size=min(k, 4 ** l), replace=False).astype(np.uint32)
+        want = np.sort(codes)
+        assert np.array_equal(nat.sort_codes(codes, l), want)
+    with pytest.raises(nat.PmsError):
+        nat.sort_codes(np.array([3, 1 << 10], dtype=np.uint32), 4)
+    with pytest.raises(nat.PmsError) as e:
+        nat.sort_codes(np.array([5, 5, 1], dtype=np.uint32), 4)
+    assert e.value.status == nat.PMS_ERR_DEVICE
+    assert nat.lib().pms_sort_codes(None, 0, 4) == nat.PMS_OK
+    assert nat.lib().pms_sort_codes(None, 3, 4) == nat.PMS_ERR_INVALID
