@@ -335,7 +335,7 @@ def bench_plain(args):
             "value", "unit", "ms_per_step", "instance_latency_ms_p50", "instance_latency_ms_p99",
             "speedup_vs_one_per_launch", "one_per_launch", "parity_vs_golden", "graph_ms_median",
             "eager", "autotuned", "candidates_per_s", "window_compares_per_s",
-            "filtered_batches", "filtered_dense_groups")}
+            "filtered_batches", "filtered_dense_groups", "per_ld_alone")}
         line["batched"]["workload"] = bl["config"]["workload"]
         nat.set_config(variant=variant, filter=filt)
     if not args.no_cpu_baseline:

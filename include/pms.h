@@ -240,6 +240,19 @@ int pms_get_config(pms_config* cfg);
 int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_path,
                  pms_config* best);
 
+/*
+ * pms_autotune_many -- (launch shape, not part of the paper's method) times
+ * the same grid on a batch itself (its own instances, eager launches), with
+ * the 16-candidate kernel beside the 64-candidate one when the current
+ * variant is AUTO, and makes the fastest the current configuration, for
+ * pms_solve_many on that batch.  Cached as for pms_autotune under a key made
+ * of the build, the device and a hash of the instances' shapes.  Instances
+ * as for pms_solve_many (capacities unused); PMS_ERR_INVALID for an invalid
+ * one.  best may be NULL.
+ */
+int pms_autotune_many(const pms_instance* inst, int32_t count, const char* cache_path,
+                      pms_config* best);
+
 /* Counters of the last solve on this device.  seq_visits counts the
  * (candidate, sequence) scans that the enhanced rule of Section III.A makes,
  * the method's own work; the others describe this library's launches.  After a device-level call

@@ -52,7 +52,7 @@ def bench_batched(args, emit=True):
     nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant],
                    filter=nat.FILTER_OFF if getattr(args, "filter", "on") == "off" else nat.FILTER_ON)
     t0 = time.perf_counter()
-    tuned = nat.autotune(20, 650, 13, 4, cache)
+    tuned = nat.autotune_many(work, cache)   # tuned on the batch itself
     tune_s = time.perf_counter() - t0
 
     for _ in range(max(1, args.warmup)):
@@ -70,10 +70,21 @@ def bench_batched(args, emit=True):
         finish_ms.append(s["host_finish_ms"])
         lat.extend(r.latency_ms for r in results)
     stats = nat.last_stats()
-    # One eager launch to split the search kernel from copies and windows.
+    # One eager launch to split the search kernel from copies and windows,
+    # then each (l, d) of the mix alone: how full its candidate slots are.
     os.environ["PMS_NO_GRAPH"] = "1"
     nat.solve_many(work, caps)
     eager = nat.last_stats()
+    per_ld = {}
+    for ld in fmgen.BATCH_LD:
+        sub = [w for w, sp in zip(work, specs) if (sp.l, sp.d) == tuple(ld)]
+        nat.solve_many(sub, [1 << 21] * len(sub))
+        sst = nat.last_stats()
+        per_ld[f"({ld[0]},{ld[1]})"] = {
+            "instances": len(sub), "search_kernel_ms": sst["kernel_ms"],
+            "slot_efficiency": sst["seq_visits"] / max(1, sst["candidate_slots"]),
+            "window_compares": sst["window_compares"], "filtered_batches": sst["filtered_batches"],
+            "single_batches": sst["single_batches"], "batches": sst["batches"]}
     del os.environ["PMS_NO_GRAPH"]
 
     parity = None
@@ -91,7 +102,12 @@ def bench_batched(args, emit=True):
                 parity = False
         parity = {"ok": parity, "instances_checked": checked}
 
-    # One instance per launch: the plain host-level path, instance by instance.
+    # One instance per launch: the plain host-level path, instance by
+    # instance, in the default configuration (the batch's tuning is for the
+    # batch).
+    tuned_cfg = nat.get_config()
+    nat.set_config(variant={"auto": 0, "lane": 1, "group16": 2, "group64": 3}[args.variant],
+                   filter=nat.FILTER_OFF if getattr(args, "filter", "on") == "off" else nat.FILTER_ON)
     for i in range(3):
         nat.solve_raw(work[i][0], work[i][1], work[i][2], capacity=caps[i])
     p0 = time.perf_counter()
@@ -102,6 +118,7 @@ def bench_batched(args, emit=True):
         per_launch_ms.append((time.perf_counter() - q0) * 1e3)
         assert st1 == nat.PMS_OK
     plain_s = time.perf_counter() - p0
+    nat.set_config(**tuned_cfg)
 
     wall = float(np.median(walls))
     cands = sum(4 ** s.l for s in specs)
@@ -136,6 +153,7 @@ def bench_batched(args, emit=True):
                            "latency_ms_p99": _pct(per_launch_ms, 99)},
         "speedup_vs_one_per_launch": plain_s / wall,
         "parity_vs_golden": parity,
+        "per_ld_alone": per_ld,
         "filtered_batches": eager["filtered_batches"],
         "filtered_dense_groups": eager["filtered_groups"],
         "batches": eager["batches"], "single_batches": eager["single_batches"],

@@ -993,6 +993,64 @@ void cache_store(const std::string& path, const std::string& key, const pms_conf
     rename((path + ".tmp").c_str(), path.c_str());
 }
 
+// Times the candidate-chunk x workgroup-shape x tail-split grid (and the
+// given variants) on these instances with eager launches, `reps` times each,
+// and returns the configuration with the shortest search-kernel time.
+int tune_grid(Ctx& c, const std::vector<Shape>& shapes,
+              const std::vector<const char* const*>& rows, const std::vector<uint32_t>& variants,
+              int reps, pms_config* best) {
+    uint64_t total = 0;
+    for (const Shape& s : shapes) total = std::max<uint64_t>(total, 1ull << (2 * s.l));
+    *best = c.cfg;
+    double best_ms = 1e300;
+    const uint32_t chunks[] = {1u << 11, 1u << 12, 1u << 13, 1u << 14, 1u << 15, 1u << 16};
+    const uint32_t waves[] = {1, 2, 4, 8};
+    const uint32_t tails[] = {0, 8};
+    for (uint32_t v : variants)
+        for (uint32_t ch : chunks) {
+            if (ch > total && ch != chunks[0]) continue;
+            // From l = 6 on items are whole multiples of 4096 candidates, so a
+            // smaller chunk gives the same plan as 4096.
+            if (ch < 4096 && total >= 4096) continue;
+            for (uint32_t w : waves)
+                for (uint32_t tail : tails) {
+                    pms_config cfg{ch, w, 0, tail, v, c.cfg.filter};
+                    Batch b;
+                    b.shape = shapes;
+                    b.rows = rows;
+                    b.out_cap.assign(shapes.size(), 0);
+                    plan_batch(b, cfg, target_items(c));
+                    PMS_TRY(stage_batch(c, b));
+                    double ms = 1e300;
+                    for (int rep = 0; rep < reps; ++rep) {
+                        PMS_TRY(run_batch(c, b, cfg, false));
+                        ms = std::min(ms, c.last.kernel_ms);
+                    }
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        *best = cfg;
+                    }
+                }
+        }
+    return PMS_OK;
+}
+
+// Cache key of a batch: the build, the device, the requested variant and
+// filter, and a hash of the instances' shapes in order.
+std::string tune_key_many(const Ctx& c, const std::vector<Shape>& shapes) {
+    uint64_t h = 0xcbf29ce484222325ull;   // FNV-1a over the shapes
+    for (const Shape& s : shapes)
+        for (int32_t v : {s.n, s.t, s.l, s.d})
+            for (int k = 0; k < 4; ++k) {
+                h ^= static_cast<uint64_t>((static_cast<uint32_t>(v) >> (8 * k)) & 0xffu);
+                h *= 0x100000001b3ull;
+            }
+    std::ostringstream o;
+    o << PMS_BUILD_ID << "/" << c.arch << "/cu" << c.cus << "/v" << c.cfg.variant << "/f"
+      << c.cfg.filter << "/batch" << shapes.size() << "/" << std::hex << h;
+    return o.str();
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1778,38 +1836,47 @@ int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_p
     const std::vector<std::string> rows = synthetic_rows(n, t, l, d, 0x1403131300ull + l * 64 + d);
     std::vector<const char*> ptrs(n);
     for (int32_t i = 0; i < n; ++i) ptrs[i] = rows[i].data();
-    const uint64_t total = 1ull << (2 * l);
-    pms_config best_cfg = c.cfg;
-    double best_ms = 1e300;
-    const uint32_t chunks[] = {1u << 11, 1u << 12, 1u << 13, 1u << 14, 1u << 15, 1u << 16};
-    const uint32_t waves[] = {1, 2, 4, 8};
-    const uint32_t tails[] = {0, 8};
-    for (uint32_t ch : chunks) {
-        if (ch > total && ch != chunks[0]) continue;
-        // From l = 6 on items are whole multiples of 4096 candidates, so a
-        // smaller chunk gives the same plan as 4096.
-        if (ch < 4096 && total >= 4096) continue;
-        for (uint32_t w : waves) {
-            for (uint32_t tail : tails) {
-                pms_config cfg{ch, w, 0, tail, c.cfg.variant, c.cfg.filter};
-                Batch b;
-                b.shape = {Shape{n, t, l, d}};
-                b.rows = {ptrs.data()};
-                b.out_cap = {0};
-                plan_batch(b, cfg, target_items(c));
-                PMS_TRY(stage_batch(c, b));
-                double ms = 1e300;
-                for (int rep = 0; rep < 3; ++rep) {
-                    PMS_TRY(run_batch(c, b, cfg, false));
-                    ms = std::min(ms, c.last.kernel_ms);
-                }
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best_cfg = cfg;
-                }
-            }
-        }
+    pms_config best_cfg;
+    PMS_TRY(tune_grid(c, {Shape{n, t, l, d}}, {ptrs.data()}, {c.cfg.variant}, 3, &best_cfg));
+    c.cfg = best_cfg;
+    if (!path.empty()) cache_store(path, key, best_cfg);
+    if (best) *best = best_cfg;
+    return PMS_OK;
+}
+
+int pms_autotune_many(const pms_instance* inst, int32_t count, const char* cache_path,
+                      pms_config* best) {
+    g_last_error.clear();
+    if (!inst || count < 1) return fail(PMS_ERR_INVALID, "NULL batch or count < 1");
+    std::vector<Shape> shapes;
+    std::vector<const char* const*> rows;
+    for (int32_t i = 0; i < count; ++i) {
+        const pms_instance& q = inst[i];
+        PMS_TRY(validate_shape(q.n, q.t, q.l, q.d));
+        PMS_TRY(validate_rows(q.seqs, q.n, q.t));
+        shapes.push_back({q.n, q.t, q.l, q.d});
+        rows.push_back(q.seqs);
     }
+    std::string path = cache_path ? cache_path : "";
+    if (path.empty())
+        if (const char* v = getenv("PMS_AUTOTUNE_CACHE")) path = v;
+    std::unique_lock<std::mutex> lk(g_ctx.mu);
+    Ctx& c = g_ctx;
+    PMS_TRY(init_ctx(c));
+    const std::string key = tune_key_many(c, shapes);
+    pms_config found;
+    if (!path.empty() && cache_lookup(path, key, &found)) {
+        c.cfg = found;
+        if (best) *best = found;
+        return PMS_OK;
+    }
+    // The requested variant, and the 16-candidate kernel beside the
+    // 64-candidate one when the choice is automatic: with low pass rates
+    // the 64-candidate groups carry many dead members.
+    std::vector<uint32_t> variants = {c.cfg.variant};
+    if (c.cfg.variant == PMS_VARIANT_AUTO) variants.push_back(PMS_VARIANT_GROUP);
+    pms_config best_cfg;
+    PMS_TRY(tune_grid(c, shapes, rows, variants, 2, &best_cfg));
     c.cfg = best_cfg;
     if (!path.empty()) cache_store(path, key, best_cfg);
     if (best) *best = best_cfg;

@@ -23,7 +23,7 @@ SYMBOLS = ["pms_solve", "pms_solve_ex", "pms_solve_intersect", "pms_solve_many",
            "pms_set_config", "pms_get_config", "pms_autotune", "pms_last_stats",
            "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev",
            "pms_valu_probe", "pms_solve_dev_noalloc", "pms_shutdown",
-           "pms_sort_codes"]
+           "pms_sort_codes", "pms_autotune_many"]
 PROBE_OPS = {"xor": 0, "bcnt": 1, "min3": 2, "or_sdwa": 3, "add": 4, "fma_f32": 5, "xor_vv": 6,
              "compare": 7, "mov_s": 8, "mov64_s": 9}
 
@@ -160,6 +160,7 @@ def _load():
         "pms_solve_dev_noalloc": ([vp, i32, i32, i32, i32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
         "pms_shutdown": ([], ctypes.c_int),
         "pms_sort_codes": ([u32p, ctypes.c_uint64, i32], ctypes.c_int),
+        "pms_autotune_many": ([P(Instance), i32, ctypes.c_char_p, P(Config)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -382,6 +383,25 @@ def autotune(n: int, t: int, l: int, d: int, cache_path: Optional[str] = None) -
     cfg = Config()
     _check(_lib.pms_autotune(n, t, l, d, cache_path.encode() if cache_path else None,
                              ctypes.byref(cfg)))
+    return cfg.as_dict()
+
+
+def autotune_many(instances: Sequence[Tuple[object, int, int]],
+                  cache_path: Optional[str] = None) -> dict:
+    """pms_autotune_many on [(seqs, l, d), ...]: tunes the launch on the batch
+    itself and makes the result the current configuration."""
+    m = len(instances)
+    rec = np.zeros(max(m, 1), dtype=_INSTANCE_DT)
+    keep = []
+    for i, (seqs, l, d) in enumerate(instances):
+        addr, k, n, t = _row_pointers(seqs)
+        keep.append(k)
+        rec[i] = (addr, n, t, l, d, 0, 0)
+    cfg = Config()
+    st = _lib.pms_autotune_many(ctypes.cast(rec.ctypes.data, ctypes.POINTER(Instance)), m,
+                                cache_path.encode() if cache_path else None, ctypes.byref(cfg))
+    del keep
+    _check(st)
     return cfg.as_dict()
 
 

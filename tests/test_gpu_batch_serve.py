@@ -108,6 +108,27 @@ def test_autotune_cache_and_results(nat, tmp_path):
         nat.set_config(reset=True)
 
 
+def test_autotune_many_on_the_batch(nat, tmp_path):
+    """Tuning on the batch itself: the cache gets the batch's key, the tuned
+    configuration gives the oracle's sets, and a second call is served from
+    the cache."""
+    path = str(tmp_path / "tune_many.json")
+    batch = mixed_batch()[:8]
+    want = oracle_sets(batch)
+    try:
+        cfg = nat.autotune_many(batch, path)
+        text = open(path).read()
+        assert "/batch8/" in text and json.loads(text)
+        assert nat.get_config() == cfg
+        assert cfg["variant"] in (0, nat.VARIANT_GROUP, nat.VARIANT_GROUP64)
+        st, got, _ = nat.solve_many(batch)
+        assert st == nat.PMS_OK and all(np.array_equal(g, w) for g, w in zip(got, want))
+        nat.set_config(reset=True)
+        assert nat.autotune_many(batch, path) == cfg
+    finally:
+        nat.set_config(reset=True)
+
+
 def test_batched_workload_matches_golden(nat):
     """The 256-instance batched workload in the benchmark's configuration."""
     path = os.path.join(GOLDEN, "batched.json")
