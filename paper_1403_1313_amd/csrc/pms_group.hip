@@ -687,6 +687,43 @@ __device__ __forceinline__ uint32_t filter_windows_any(uint32_t P, cu32* W, uint
     }
 }
 
+// Window filter attempt for a group batch (64-candidate kernel): counts the
+// live lanes' blocks of 64 consecutive groups (key = the group's first l - 6
+// bases), and when they are at most `lim` and fit the table lanes, runs
+// filter_windows.  Returns its dense group count (kNoFit otherwise) with the
+// block count and the lane's block.
+__device__ __forceinline__ uint32_t try_filter(uint32_t lim, uint32_t key, bool live, uint32_t P,
+                                               cu32* W, uint32_t groups, int d, uint32_t* svt,
+                                               uint32_t& fblk, uint32_t& fmyb) {
+    fblk = 0;
+    fmyb = 0;
+    if (lim == 0u || P < 3u || groups > 64u) return kNoFit;
+    const uint32_t lane = lane_id();
+    const uint32_t kmax = 64u / groups < lim ? 64u / groups : lim;
+    uint64_t todo = ballot(live);
+    for (; todo != 0 && fblk <= kmax; ++fblk) {
+        const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
+            static_cast<int>(key), static_cast<int>(__builtin_ctzll(todo))));
+        todo &= ~ballot(key == v);
+    }
+    if (todo != 0 || fblk < 1u || fblk > kmax) return kNoFit;
+    uint32_t kv = 0, tj = 64u;
+    todo = ballot(live);
+    for (uint32_t k = 0; todo != 0; ++k) {
+        const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
+            static_cast<int>(key), static_cast<int>(__builtin_ctzll(todo))));
+        const bool mine = key == v;
+        todo &= ~ballot(mine);
+        const uint32_t b = k * groups;
+        if (mine) fmyb = k;
+        if (lane - b < groups) {
+            kv = v;
+            tj = lane - b;
+        }
+    }
+    return filter_windows_any(P, W, groups, fblk, kv, tj, d, svt);
+}
+
 // Scan of the nv dense window groups filter_windows left in `svt` (stride
 // words each) for the lane's group of 64 candidates: myb = the lane's block
 // in the batch, low = its last three prefix bases.  Per group the block's
@@ -1029,7 +1066,11 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         }
 
         if (kSingles && single) {
-            // One sequence scan for up to 64 single candidates.
+            // One sequence scan for up to 64 single candidates.  (The window
+            // filter, which single batches of up to three blocks of 4096
+            // candidates could use as well, took their VALU count down by
+            // two thirds and left the kernel time unchanged: its dependent
+            // LDS round trips cost what the scan's instructions did.)
             const bool live = alive != 0;
             const bool ok = live && scan_single_any(P + S, W + s * row, groups, prefix, d);
             visits += live ? 1u : 0u;
@@ -1070,54 +1111,46 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         // One sequence scan for 64 groups.
         Mask pass;
         if constexpr (S == 3) {
-            // Blocks of 64 consecutive groups among the live lanes, each
-            // given `groups` table lanes; when they all fit, the window filter
-            // (dense window groups of the windows that can pass) or the
-            // shared-prefix scan of every window.  (Counted first with
-            // wave-uniform values only, then the per-lane block data inside
-            // the branch that uses it: computed ahead of the branch, it cost
-            // the general scan registers.)
-            uint32_t nblk = 0;
-            if (P >= 3u && groups <= 64u) {
+            // The window filter's dense groups when it ran; otherwise, when
+            // the live lanes' blocks of 64 consecutive groups all fit the
+            // table lanes, the shared-prefix scan of every window.  (Counted
+            // first with wave-uniform values only, then the per-lane block
+            // data inside the branch that uses it: computed ahead of the
+            // branch, it cost the general scan registers.)
+            bool done = false;
+            uint32_t fblk, fmyb;
+            const uint32_t nv = try_filter(fmax, prefix >> 6, alive != 0, P, W + s * row, groups,
+                                           d, svt, fblk, fmyb);
+            if (nv != kNoFit) {
+                pass = scan_filtered(nv, 12u + 8u * fblk, fmyb, svt, prefix & 63u, alive);
+                ++filtered;
+                filtered_groups += nv;
+                done = true;
+            } else if (P >= 3u && groups * 12u <= PMS_SVT_WORDS) {
                 const uint32_t kmax = 64u / groups;
+                uint32_t nblk = 0;
                 uint64_t todo = ballot(alive != 0);
                 for (; todo != 0 && nblk <= kmax; ++nblk) {
                     const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
                         static_cast<int>(prefix >> 6), static_cast<int>(__builtin_ctzll(todo))));
                     todo &= ~ballot((prefix >> 6) == v);
                 }
-                if (todo != 0 || nblk > kmax) nblk = 0;
-            }
-            const bool use_filter = nblk != 0 && nblk <= fmax;
-            const bool use_shared = nblk != 0 && groups * 12u <= PMS_SVT_WORDS;
-            bool done = false;
-            if (use_filter || use_shared) {
-                const uint32_t hi = prefix >> 6;
-                uint32_t kv = 0, tj = 64u, myb = 0;
-                uint64_t todo = ballot(alive != 0);
-                for (uint32_t k = 0; todo != 0; ++k) {
-                    const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
-                        static_cast<int>(hi), static_cast<int>(__builtin_ctzll(todo))));
-                    const bool mine = hi == v;
-                    todo &= ~ballot(mine);
-                    const uint32_t b = k * groups;
-                    if (mine) myb = k;
-                    if (lane - b < groups) {
-                        kv = v;
-                        tj = lane - b;
+                if (todo == 0 && nblk <= kmax) {
+                    const uint32_t hi = prefix >> 6;
+                    uint32_t kv = 0, tj = 64u, myb = 0;
+                    todo = ballot(alive != 0);
+                    for (uint32_t k = 0; todo != 0; ++k) {
+                        const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
+                            static_cast<int>(hi), static_cast<int>(__builtin_ctzll(todo))));
+                        const bool mine = hi == v;
+                        todo &= ~ballot(mine);
+                        const uint32_t b = k * groups;
+                        if (mine) myb = k;
+                        if (lane - b < groups) {
+                            kv = v;
+                            tj = lane - b;
+                        }
                     }
-                }
-                if (use_filter) {
-                    const uint32_t nv =
-                        filter_windows_any(P, W + s * row, groups, nblk, kv, tj, d, svt);
-                    if (nv != kNoFit) {
-                        pass = scan_filtered(nv, 12u + 8u * nblk, myb, svt, prefix & 63u, alive);
-                        ++filtered;
-                        filtered_groups += nv;
-                        done = true;
-                    }
-                }
-                if (!done && use_shared) {
                     pass = scan_group_shared_any(P, W + s * row, groups, kv, tj, myb * groups,
                                                  prefix & 63u, d, alive, svt);
                     done = true;
@@ -1276,8 +1309,11 @@ pms_search_group_kernel(const pms_dev_instance* __restrict__ insts,
 }
 
 // At most 4 wavefronts per workgroup: the 64 accumulators per lane need more
-// than the 128 VGPRs a 16-wavefront workgroup could give each lane.
+// than the 128 VGPRs a 16-wavefront workgroup could give each lane.  At least
+// three wavefronts per SIMD (at most 168 VGPRs): issue rates with two are far
+// lower, and left to itself the scheduler would trade the third for registers.
 extern "C" __global__ void __launch_bounds__(PMS_GROUP64_MAX_THREADS)
+__attribute__((amdgpu_waves_per_eu(3)))
 pms_search_group64_kernel(const pms_dev_instance* __restrict__ insts,
                           const pms_work_item* __restrict__ work, uint32_t n_work,
                           pms_dev_state* __restrict__ state, pms_dev_counters* __restrict__ ctr,
