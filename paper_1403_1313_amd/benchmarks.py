@@ -176,6 +176,7 @@ def bench_serving(args):
     inflight = int(os.environ.get("PMS_SERVE_INFLIGHT", "2"))
     min_step = os.environ.get("PMS_SERVE_MIN_STEP_MS")
     min_step = float(min_step) if min_step else step_ms / 2
+    lookahead = float(os.environ.get("PMS_SERVE_LOOKAHEAD_MS", "0.25"))
     out = []
     for rate in rates:
         # about a second of arrivals, at least 60 and at most 300 requests
@@ -183,7 +184,8 @@ def bench_serving(args):
         stream = fmgen.serving_stream(count, rate)
         reqs = [(t_arr, spec.make()) for t_arr, spec in stream]
         with Server(mem_budget=256 << 20, step_ms=step_ms, oldest_share=oldest,
-                    max_inflight=inflight, min_step_ms=min_step) as srv:
+                    max_inflight=inflight, min_step_ms=min_step,
+                    lookahead_ms=lookahead) as srv:
             # warm up the kernels and allocator
             srv.submit(reqs[0][1].seqs, reqs[0][1].l, reqs[0][1].d).result()
             t0 = time.perf_counter()
@@ -197,10 +199,14 @@ def bench_serving(args):
             span = max(r.finished for r in results) - t0
             stats = dict(srv.stats)
             stats["compares_per_s_estimate"] = srv.rate
-        lat = [r.latency_s * 1e3 for r in results]
+        # Latency from each request's scheduled arrival (as for the FIFO leg
+        # below), so that a client that submits late is not credited.
+        lat = [(r.finished - (t0 + t_arr)) * 1e3 for (t_arr, _), r in zip(reqs, results)]
         # Where the time of the slowest requests goes (host clock, ms).
-        worst = sorted(results, key=lambda r: r.latency_s)[-max(1, len(results) // 100):]
-        parts = {"admit": [1e3 * (r.admitted - r.arrival) for r in worst],
+        order = sorted(range(len(results)), key=lambda i: lat[i])[-max(1, len(results) // 100):]
+        worst = [results[i] for i in order]
+        parts = {"submit_late": [1e3 * (results[i].arrival - (t0 + reqs[i][0])) for i in order],
+                 "admit": [1e3 * (r.admitted - r.arrival) for r in worst],
                  "to_first_step": [1e3 * (r.launched - r.admitted) for r in worst],
                  "steps": [1e3 * (r.retired - r.launched) for r in worst],
                  "finish": [1e3 * (r.finished - r.retired) for r in worst],
@@ -219,11 +225,21 @@ def bench_serving(args):
         # Every served result against the same request solved alone by pms_solve.
         same = sum(1 for r, (st, cnt, codes) in zip(results, fifo_codes)
                    if st == nat.PMS_OK and r.count == cnt and np.array_equal(r.motifs, codes))
+        # Latency by (l,d): the (15,4) requests set the tail.
+        by_ld = {}
+        for (t_arr, inst), srv_ms, fifo_ms in zip(reqs, lat, fifo_lat):
+            by_ld.setdefault(f"({inst.l},{inst.d})", ([], []))
+            by_ld[f"({inst.l},{inst.d})"][0].append(srv_ms)
+            by_ld[f"({inst.l},{inst.d})"][1].append(fifo_ms)
+        by_ld = {k: {"requests": len(a), "server_ms_p50": _pct(a, 50), "server_ms_max": max(a),
+                     "fifo_ms_p50": _pct(b, 50), "fifo_ms_max": max(b)}
+                 for k, (a, b) in sorted(by_ld.items())}
         out.append({"rate": rate, "requests": count, "solves_per_s": count / span,
                     "latency_ms_p50": _pct(lat, 50), "latency_ms_p99": _pct(lat, 99),
                     "server_stats": stats,
                     "slowest_1pct_mean_ms": {k: float(np.mean(v)) for k, v in parts.items()},
                     "parity_vs_solo": {"ok": same == count, "requests_equal": same},
+                    "latency_by_ld": by_ld,
                     "one_per_launch_fifo": {"solves_per_s": count / fifo_span,
                                             "latency_ms_p50": _pct(fifo_lat, 50),
                                             "latency_ms_p99": _pct(fifo_lat, 99)}})
@@ -237,7 +253,8 @@ def bench_serving(args):
                                "(9,2),(11,3),(13,4),(15,4) weighted 4:3:2:1, n in [10,30], "
                                "t in [300,1000], master seed 1313", "rates": rates,
                    "requests": [r["requests"] for r in out], "step_ms": step_ms,
-                   "oldest_share": oldest, "max_inflight": inflight, "min_step_ms": min_step},
+                   "oldest_share": oldest, "max_inflight": inflight, "min_step_ms": min_step,
+                   "lookahead_ms": lookahead},
         "sweep": out,
     }
     print(json.dumps(line), flush=True)

@@ -196,7 +196,7 @@ class Server:
                  device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
                  items_per_step: int = 8192, oldest_share: float = 0.5,
                  min_step_ms: Optional[float] = None, backlog_share: float = 0.25,
-                 step_timeout_s: float = 60.0):
+                 step_timeout_s: float = 60.0, lookahead_ms: float = 0.25):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)
@@ -218,6 +218,13 @@ class Server:
         self.oldest_share = float(oldest_share)
         self.copy_stream = torch.cuda.Stream(self.dev)
         self.max_inflight = int(max_inflight)
+        # A further step is queued behind the ones in flight only once they
+        # are expected to end within lookahead_ms (from the estimated device
+        # rate): enough to hide the host's turn between steps, short enough
+        # that a request arriving meanwhile waits behind about one step, not
+        # max_inflight of them.
+        self.lookahead_s = lookahead_ms * 1e-3
+        self.queue_end = 0.0
         # Steps run a grouped kernel, whose windows are bit-sliced: 64
         # candidates per lane, or 16 when a step holds an l = 2 request.
         self.config = dict(config or {})
@@ -470,6 +477,8 @@ class Server:
     def _launch(self) -> bool:
         if not self.idle_bufs:
             return False
+        if self.inflight and time.perf_counter() < self.queue_end - self.lookahead_s:
+            return False
         buf = self.idle_bufs[-1]
         n_items = self._build_step(buf)
         if n_items == 0:
@@ -519,6 +528,7 @@ class Server:
             buf.done = torch.cuda.Event()
             buf.done.record(self.stream)
         buf.launched = time.perf_counter()
+        self.queue_end = max(buf.launched, self.queue_end) + buf.compares / self.rate
         for r in buf.reqs:
             r.inflight += 1
             r.steps += 1
@@ -649,7 +659,8 @@ class Server:
         """Waits for a step to complete, up to the step timeout from its
         launch (polling: an event wait could not be abandoned).  Returns False
         as soon as a request arrives, so that it is admitted and can join the
-        next step while this one runs."""
+        next step while this one runs, or when the next step should be
+        queued behind this one."""
         deadline = buf.launched + self.step_timeout_s
         while not buf.done.query():
             if time.perf_counter() > deadline:
@@ -658,6 +669,9 @@ class Server:
                                   "after its launch")
             if self.waiting and self.free_slots:
                 return False
+            if (self.idle_bufs and time.perf_counter() >= self.queue_end - self.lookahead_s
+                    and any(r.cursor < r.total for r in self.active)):
+                return False    # time to queue the next step behind this one
             time.sleep(0)   # yield only: the step's end is seen within microseconds
         return True
 
