@@ -23,7 +23,7 @@
  *
  * Modes:
  *   ORACLE_BRUTE (0): unpruned.  Every candidate is compared with every
- *       window of every sequence, and only then is the verdict taken.
+ *       window of every sequence, and only then is the decision taken.
  *   ORACLE_SKIP  (1): the enhanced rule of Section III.A: the first sequence
  *       with no matching window rejects the candidate and the remaining
  *       sequences are not examined.  It also counts the sequence visits so
