@@ -412,6 +412,19 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
                     const pms_config* cfg, void* stream);
 
 /*
+ * pms_fill_work_items -- host helper for callers that build the work tables
+ * of pms_step_launch themselves (index ranges of Section IV.A): writes the
+ * items covering candidates [begin, begin + count) of instance `inst`, in
+ * ranges of item_len candidates (the last one shorter), to out[0 ..),
+ * stopping after max_items.  Returns the number of items written; the
+ * candidates they cover are min(count, items x item_len).  -1 (nothing
+ * written) for item_len 0, NULL out with max_items > 0, or a range that
+ * passes 2^32 candidates.
+ */
+int32_t pms_fill_work_items(uint64_t begin, uint64_t count, uint32_t item_len, uint32_t inst,
+                            pms_work_item* out, int32_t max_items);
+
+/*
  * pms_solve_dev -- the whole device part of one solve (Section III.A's method
  * on device buffers) on the caller's stream:
  * builds windows, lays out work items, and runs the search.  dev_seqs holds

@@ -5,6 +5,7 @@ GPU: ``pms_solve`` called for each instance in turn.
 """
 from __future__ import annotations
 
+import gc
 import hashlib
 import json
 import os
@@ -177,17 +178,28 @@ def bench_serving(args):
     min_step = os.environ.get("PMS_SERVE_MIN_STEP_MS")
     min_step = float(min_step) if min_step else step_ms / 2
     lookahead = float(os.environ.get("PMS_SERVE_LOOKAHEAD_MS", "0.25"))
+    idle_wait = float(os.environ.get("PMS_SERVE_IDLE_WAIT_MS", "1.0"))
     out = []
     for rate in rates:
         # about a second of arrivals, at least 60 and at most 300 requests
-        count = int(fixed) if fixed else int(min(300, max(60, rate)))
+        # 15 s of arrivals at 20 req/s, 5 s at 200, 1000 requests at most:
+        # enough that the 99th percentile is not one request.
+        count = int(fixed) if fixed else int(min(1000, max(300, 25 * rate)))
         stream = fmgen.serving_stream(count, rate)
         reqs = [(t_arr, spec.make()) for t_arr, spec in stream]
         with Server(mem_budget=256 << 20, step_ms=step_ms, oldest_share=oldest,
                     max_inflight=inflight, min_step_ms=min_step,
-                    lookahead_ms=lookahead) as srv:
-            # warm up the kernels and allocator
-            srv.submit(reqs[0][1].seqs, reqs[0][1].l, reqs[0][1].d).result()
+                    lookahead_ms=lookahead, idle_wait_ms=idle_wait) as srv:
+            # Warm up the kernels and allocator on one request of each (l,d)
+            # of the stream; no garbage collection inside the timed loops.
+            seen = {}
+            for _, inst in reqs:
+                seen.setdefault((inst.l, inst.d), inst)
+            for inst in seen.values():
+                srv.submit(inst.seqs, inst.l, inst.d).result()
+            time.sleep(0.05)
+            gc.collect()
+            gc.disable()
             t0 = time.perf_counter()
             futs = []
             for t_arr, inst in reqs:
@@ -196,6 +208,7 @@ def bench_serving(args):
                     time.sleep(t_arr - now)
                 futs.append(srv.submit(inst.seqs, inst.l, inst.d))
             results = [f.result() for f in futs]
+            gc.enable()
             span = max(r.finished for r in results) - t0
             stats = dict(srv.stats)
             stats["compares_per_s_estimate"] = srv.rate
@@ -214,6 +227,8 @@ def bench_serving(args):
         # the same arrivals served one instance per launch, first come first served
         t1 = time.perf_counter()
         fifo_lat, fifo_codes = [], []
+        gc.collect()
+        gc.disable()
         for t_arr, inst in reqs:
             now = time.perf_counter() - t1
             if t_arr > now:
@@ -222,6 +237,7 @@ def bench_serving(args):
             fifo_lat.append((time.perf_counter() - t1 - t_arr) * 1e3)
             fifo_codes.append((st, cnt, codes))
         fifo_span = time.perf_counter() - t1
+        gc.enable()
         # Every served result against the same request solved alone by pms_solve.
         same = sum(1 for r, (st, cnt, codes) in zip(results, fifo_codes)
                    if st == nat.PMS_OK and r.count == cnt and np.array_equal(r.motifs, codes))
@@ -254,7 +270,7 @@ def bench_serving(args):
                                "t in [300,1000], master seed 1313", "rates": rates,
                    "requests": [r["requests"] for r in out], "step_ms": step_ms,
                    "oldest_share": oldest, "max_inflight": inflight, "min_step_ms": min_step,
-                   "lookahead_ms": lookahead},
+                   "lookahead_ms": lookahead, "idle_wait_ms": idle_wait},
         "sweep": out,
     }
     print(json.dumps(line), flush=True)

@@ -1085,6 +1085,18 @@ int pms_sort_codes(uint32_t* codes, uint64_t count, int32_t l) {
     return PMS_OK;
 }
 
+int32_t pms_fill_work_items(uint64_t begin, uint64_t count, uint32_t item_len, uint32_t inst,
+                            pms_work_item* out, int32_t max_items) {
+    if (item_len == 0 || (max_items > 0 && !out)) return -1;
+    if (begin > (1ull << 32) || count > (1ull << 32) - begin) return -1;
+    int32_t k = 0;
+    for (uint64_t at = begin, end = begin + count; at < end && k < max_items; at += item_len, ++k) {
+        const uint64_t len = std::min<uint64_t>(item_len, end - at);
+        out[k] = pms_work_item{at, static_cast<uint32_t>(len), inst};
+    }
+    return k;
+}
+
 void pms_decode(uint32_t code, int32_t l, char* out) {
     if (!out || l < 1 || l > PMS_MAX_L) return;
     for (int32_t p = 0; p < l; ++p) out[p] = "ACGT"[(code >> (2 * (l - 1 - p))) & 3u];

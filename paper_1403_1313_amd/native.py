@@ -23,7 +23,7 @@ SYMBOLS = ["pms_solve", "pms_solve_ex", "pms_solve_intersect", "pms_solve_many",
            "pms_set_config", "pms_get_config", "pms_autotune", "pms_last_stats",
            "pms_window_stride", "pms_build_windows", "pms_step_launch", "pms_solve_dev",
            "pms_valu_probe", "pms_solve_dev_noalloc", "pms_shutdown",
-           "pms_sort_codes", "pms_autotune_many"]
+           "pms_sort_codes", "pms_autotune_many", "pms_fill_work_items"]
 PROBE_OPS = {"xor": 0, "bcnt": 1, "min3": 2, "or_sdwa": 3, "add": 4, "fma_f32": 5, "xor_vv": 6,
              "compare": 7, "mov_s": 8, "mov64_s": 9}
 
@@ -161,6 +161,8 @@ def _load():
         "pms_shutdown": ([], ctypes.c_int),
         "pms_sort_codes": ([u32p, ctypes.c_uint64, i32], ctypes.c_int),
         "pms_autotune_many": ([P(Instance), i32, ctypes.c_char_p, P(Config)], ctypes.c_int),
+        "pms_fill_work_items": ([ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                 vp, i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -358,6 +360,14 @@ def sort_codes(codes: np.ndarray, l: int) -> np.ndarray:
     _check(_lib.pms_sort_codes(codes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                int(codes.size), int(l)))
     return codes
+
+
+def fill_work_items(begin: int, count: int, item_len: int, inst: int, out_ptr: int,
+                    max_items: int) -> int:
+    """pms_fill_work_items into host memory at out_ptr (16-byte records):
+    the number of items written (-1 for invalid arguments)."""
+    return int(_lib.pms_fill_work_items(int(begin), int(count), int(item_len), int(inst),
+                                        ctypes.c_void_p(int(out_ptr)), int(max_items)))
 
 
 def decode(code: int, l: int) -> str:

@@ -111,28 +111,31 @@ class _PinnedRing:
         self.torch = torch
         self.slot_bytes = slot_bytes
         self.buf = torch.zeros(slots * slot_bytes, dtype=torch.uint8).pin_memory()
-        self.events = [None] * slots
+        self.host = self.buf.numpy()
+        self.events = [torch.cuda.Event() for _ in range(slots)]
+        self.pending = [False] * slots
         self.next = 0
 
-    def stage(self, data: bytes):
-        """A pinned uint8 tensor holding `data` (None if it does not fit a slot)."""
-        if len(data) > self.slot_bytes:
+    def stage(self, data):
+        """A pinned uint8 tensor holding `data` (bytes or a uint8 array; None
+        if it does not fit a slot)."""
+        size = len(data)
+        if size > self.slot_bytes:
             return None, None
         k = self.next
         self.next = (k + 1) % len(self.events)
-        if self.events[k] is not None:
+        if self.pending[k]:
             self.events[k].synchronize()
-        view = self.buf[k * self.slot_bytes:k * self.slot_bytes + len(data)]
-        view.numpy()[:] = np.frombuffer(data, dtype=np.uint8)
-        return view, k
+        at = k * self.slot_bytes
+        self.host[at:at + size] = np.frombuffer(data, dtype=np.uint8) if isinstance(data, bytes) else data
+        return self.buf[at:at + size], k
 
     def used(self, k, stream):
         """Marks slot k as read by the copies just queued on `stream`."""
         if k is None:
             return
-        ev = self.torch.cuda.Event()
-        ev.record(stream)
-        self.events[k] = ev
+        self.events[k].record(stream)
+        self.pending[k] = True
 
 
 class _PinnedPool:
@@ -156,6 +159,10 @@ class _PinnedPool:
             self.free.setdefault(buf.numel(), []).append(buf)
 
 
+_STATE_DTYPE = np.dtype([("count", "<u8"), ("visits", "<u8"), ("t_done", "<u8"),
+                         ("items_left", "<u4"), ("reserved", "<u4")])
+
+
 class _StepBuf:
     """Pinned staging and device copies of one step's tables."""
 
@@ -166,10 +173,12 @@ class _StepBuf:
         self.d_ctr = torch.zeros(ctypes.sizeof(nat.DevCounters) // 8, dtype=torch.int64, device=dev)
         self.h_ctr = torch.zeros(ctypes.sizeof(nat.DevCounters) // 8, dtype=torch.int64).pin_memory()
         self.h_state = torch.zeros(MAX_SLOTS * 32, dtype=torch.uint8).pin_memory()
-        self.event = None           # end of the search launch (timed)
+        # Recorded again by every launch of this buffer (it is only reused
+        # after the step that recorded them has retired).
+        self.start = torch.cuda.Event(enable_timing=True)
+        self.event = torch.cuda.Event(enable_timing=True)   # end of the search launch
+        self.done = torch.cuda.Event()                      # state snapshot copied to the host
         self.launched = 0.0         # host time of the launch (step watchdog)
-        self.done = None            # state snapshot copied to the host
-        self.start = None
         self.compares = 0.0         # estimated window compares of the step
         self.budget = 0.0           # the step's budget when it was built
         self.reqs: List[_Req] = []
@@ -196,7 +205,8 @@ class Server:
                  device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
                  items_per_step: int = 8192, oldest_share: float = 0.5,
                  min_step_ms: Optional[float] = None, backlog_share: float = 0.25,
-                 step_timeout_s: float = 60.0, lookahead_ms: float = 0.25):
+                 step_timeout_s: float = 60.0, lookahead_ms: float = 0.25,
+                 idle_wait_ms: float = 1.0):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)
@@ -225,6 +235,10 @@ class Server:
         # max_inflight of them.
         self.lookahead_s = lookahead_ms * 1e-3
         self.queue_end = 0.0
+        # An idle server thread waits for requests in slices of idle_wait_ms
+        # (a submit wakes it at once either way; short slices keep its wake-up
+        # from a long idle period quick).
+        self.idle_wait_s = idle_wait_ms * 1e-3
         # Steps run a grouped kernel, whose windows are bit-sliced: 64
         # candidates per lane, or 16 when a step holds an l = 2 request.
         self.config = dict(config or {})
@@ -310,8 +324,8 @@ class Server:
         if not (1 <= n <= nat.PMS_MAX_N and 1 <= l <= nat.PMS_MAX_L and l <= t <= nat.PMS_MAX_T
                 and 0 <= d <= l):
             raise nat.PmsError(nat.PMS_ERR_INVALID, f"size out of range n={n} t={t} l={l} d={d}")
-        ok = np.isin(m | 0x20, np.frombuffer(b"acgt", dtype=np.uint8))
-        if not ok.all():
+        f = m | 0x20   # fold upper case onto lower
+        if not ((f == 97) | (f == 99) | (f == 103) | (f == 116)).all():   # a c g t
             raise nat.PmsError(nat.PMS_ERR_INVALID, "a byte is not A/C/G/T")
 
     def _admit(self):
@@ -365,15 +379,21 @@ class Server:
         torch = self.torch
         req.slot = self.free_slots.pop()
         raw = req.seqs.reshape(-1)
-        staged, k = self.ring.stage(raw.tobytes())
+        staged, k = self.ring.stage(raw)
         with torch.cuda.stream(self.stream):
-            req.dev_seqs = torch.empty(raw.size, dtype=torch.uint8, device=self.dev)
+            # One device block per request: rows, window table and output,
+            # each starting on a 256-byte boundary.
+            seq_w = (raw.size + 255) // 256 * 64
+            win_w = req.n * req.stride
+            out_at = seq_w + (win_w + 63) // 64 * 64
+            block = torch.empty(out_at + max(req.cap, 1), dtype=torch.int32, device=self.dev)
+            req.dev_seqs = block[:seq_w].view(torch.uint8)[:raw.size]
+            req.dev_win = block[seq_w:seq_w + win_w]
+            req.dev_out = block[out_at:]
             if staged is None:
                 staged = torch.from_numpy(raw).pin_memory()
             req.dev_seqs.copy_(staged, non_blocking=True)
             self.ring.used(k, self.stream)
-            req.dev_win = torch.empty(req.n * req.stride, dtype=torch.int32, device=self.dev)
-            req.dev_out = torch.empty(max(req.cap, 1), dtype=torch.int32, device=self.dev)
         nat.build_windows(req.dev_seqs, req.n, req.t, req.l, req.dev_win, None, stream=self.stream,
                           layout=nat.LAYOUT_BITSLICED)
         self._write_slot(req)
@@ -437,9 +457,9 @@ class Server:
         if left > 0:
             shares[oldest.rid] += left
         item_compares = budget / self.items_per_step
-        parts = []
         per_req: Dict[int, int] = {}
         used = 0
+        table = buf.h_work.data_ptr()
         for r in order:
             cands = int(shares.get(r.rid, 0.0) / r.cost_per_cand)
             cands = max(64, (cands + 63) // 64 * 64)
@@ -454,25 +474,20 @@ class Server:
             # 64-candidate groups), so that it runs on many wavefronts.
             size = min(size, max(64, cands // 1024))
             size = max(64, (size + 63) // 64 * 64)
-            k = min(-(-cands // size), room)
-            begins = r.cursor + np.arange(k, dtype=np.uint64) * np.uint64(size)
-            lens = np.minimum(np.uint64(size), np.uint64(r.cursor + cands) - begins)
-            rec = np.zeros(k, dtype=[("begin", "<u8"), ("len", "<u4"), ("inst", "<u4")])
-            rec["begin"] = begins
-            rec["len"] = lens.astype(np.uint32)
-            rec["inst"] = r.slot
-            parts.append(rec)
-            r.cursor += int(lens.sum())
-            buf.compares += float(lens.sum()) * r.cost_per_cand
+            # Items written straight into the pinned table (pms_work_item records).
+            k = nat.fill_work_items(r.cursor, cands, size, r.slot, table + 16 * used, room)
+            if k <= 0:
+                continue
+            covered = min(cands, k * size)
+            r.cursor += covered
+            buf.compares += float(covered) * r.cost_per_cand
             per_req[r.slot] = k
             used += k
-        if not parts:
+        if used == 0:
             return 0
-        arr = np.concatenate(parts)
-        buf.h_work.numpy()[:arr.nbytes] = arr.view(np.uint8)
         buf.reqs = [r for r in live if r.slot in per_req]
         buf.items_per_req = per_req
-        return int(arr.size)
+        return used
 
     def _launch(self) -> bool:
         if not self.idle_bufs:
@@ -496,7 +511,6 @@ class Server:
         with torch.cuda.stream(self.stream):
             buf.d_work[:n_items * 16].copy_(buf.h_work[:n_items * 16], non_blocking=True)
             buf.d_ctr.zero_()
-            buf.start = torch.cuda.Event(enable_timing=True)
             buf.start.record(self.stream)
         try:
             nat.step_launch(self.d_insts, MAX_SLOTS, max_n, buf.d_work, n_items, self.d_state,
@@ -509,7 +523,6 @@ class Server:
             self._fail(reqs, e)
             return True
         with torch.cuda.stream(self.stream):
-            buf.event = torch.cuda.Event(enable_timing=True)
             buf.event.record(self.stream)
             buf.h_state.copy_(self.d_state, non_blocking=True)
             buf.h_ctr.copy_(buf.d_ctr, non_blocking=True)
@@ -525,7 +538,6 @@ class Server:
                     self.pool.put(r.h_out)
                     r.h_out = self.pool.get(k)
                     r.h_out[:k].copy_(r.dev_out[:k], non_blocking=True)
-            buf.done = torch.cuda.Event()
             buf.done.record(self.stream)
         buf.launched = time.perf_counter()
         self.queue_end = max(buf.launched, self.queue_end) + buf.compares / self.rate
@@ -549,9 +561,8 @@ class Server:
             measured = buf.compares / (ms * 1e-3)
             self.rate = min(max(0.7 * self.rate + 0.3 * measured, 1e11), 1e16)
             self.step_compares = self.step_s * self.rate
-        states = np.frombuffer(buf.h_state.numpy().tobytes(), dtype=[
-            ("count", "<u8"), ("visits", "<u8"), ("t_done", "<u8"), ("items_left", "<u4"),
-            ("reserved", "<u4")])
+        # A view of the pinned snapshot (read below, before the buffer's next use).
+        states = buf.h_state.numpy().view(_STATE_DTYPE)
         ctr = nat.DevCounters.from_buffer_copy(buf.h_ctr.numpy().tobytes())
         reqs, buf.reqs = buf.reqs, []
         self.idle_bufs.append(buf)
@@ -691,7 +702,7 @@ class Server:
                     if not self.running and not busy:
                         return
                     if not busy:
-                        self.cv.wait(timeout=0.05)
+                        self.cv.wait(timeout=self.idle_wait_s)
                         continue
                     self._admit()
                 launched = False

@@ -246,6 +246,19 @@ void check_cache(const char* dir) {
 
 // The C ABI's host-side error paths; with no device, valid calls report a
 // device error and write nothing.
+void check_fill_work_items() {
+    pms_work_item w[8];
+    CHECK(pms_fill_work_items(4096, 64 * 5 + 7, 64, 3, w, 8) == 6);
+    CHECK(w[0].begin == 4096 && w[0].len == 64 && w[0].inst == 3);
+    CHECK(w[5].begin == 4096 + 64 * 5 && w[5].len == 7);
+    CHECK(pms_fill_work_items(0, 1000, 64, 1, w, 8) == 8 && w[7].begin == 448);
+    CHECK(pms_fill_work_items(0, 0, 64, 1, w, 8) == 0);
+    CHECK(pms_fill_work_items(0, 10, 0, 1, w, 8) == -1);
+    CHECK(pms_fill_work_items(0, 10, 64, 1, nullptr, 8) == -1);
+    CHECK(pms_fill_work_items(1, 1ull << 32, 64, 1, w, 8) == -1);
+    CHECK(pms_fill_work_items(0, 1ull << 32, 1u << 31, 1, w, 8) == 2 && w[1].len == (1u << 31));
+}
+
 void check_abi() {
     uint32_t out[4] = {7, 7, 7, 7};
     uint64_t cnt = 4;
@@ -281,6 +294,7 @@ int main(int argc, char** argv) {
     check_sort(rng);
     check_cache(argc > 1 ? argv[1] : "/tmp");
     check_abi();
+    check_fill_work_items();
     if (failures) {
         std::fprintf(stderr, "%d checks failed\n", failures);
         return 1;

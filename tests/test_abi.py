@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 20
+    assert len(names) == 21
     assert sorted(nat.SYMBOLS) == names
     lib = ctypes.CDLL(nat.LIB_PATH)
     for name in names:
@@ -312,3 +312,23 @@ def test_sort_codes():
     assert e.value.status == nat.PMS_ERR_DEVICE
     assert nat.lib().pms_sort_codes(None, 0, 4) == nat.PMS_OK
     assert nat.lib().pms_sort_codes(None, 3, 4) == nat.PMS_ERR_INVALID
+
+
+def test_fill_work_items():
+    """pms_fill_work_items (host only): the same records as writing the
+    ranges out by hand, the max_items cut, and its argument checks."""
+    rec = np.dtype([("begin", "<u8"), ("len", "<u4"), ("inst", "<u4")])
+    for begin, count, size, inst, room in [(0, 4 ** 8, 4096, 3, 100), (4096, 1000, 64, 7, 100),
+                                           (64, 64 * 37 + 5, 64, 0, 10), (0, 1 << 32, 1 << 31, 1, 9),
+                                           (100, 0, 64, 2, 4)]:
+        out = np.zeros(room, dtype=rec)
+        k = nat.fill_work_items(begin, count, size, inst, out.ctypes.data, room)
+        want_begins = np.arange(begin, begin + count, size, dtype=np.uint64)[:room]
+        assert k == want_begins.size
+        assert np.array_equal(out["begin"][:k], want_begins)
+        assert np.array_equal(out["len"][:k],
+                              np.minimum(size, begin + count - want_begins).astype(np.uint32))
+        assert np.all(out["inst"][:k] == inst) and np.all(out["begin"][k:] == 0)
+    assert nat.fill_work_items(0, 10, 0, 0, 0, 0) == -1
+    assert nat.fill_work_items(0, 10, 64, 0, 0, 5) == -1
+    assert nat.fill_work_items(1, 1 << 32, 64, 0, np.zeros(1, dtype=rec).ctypes.data, 1) == -1
