@@ -266,6 +266,9 @@ Estimate estimate(const Shape& s) {
 // Batch::out_cap value asking for no device output at all (a size query:
 // the kernel's count is exact without it).
 constexpr uint64_t kCountOnly = ~0ull;
+// Batches of more instances than this bring their codes back through one
+// device-side gather and one copy instead of a copy per instance.
+constexpr size_t kGatherMin = 4;
 
 // Device output slots reserved for one instance before its count is known.
 // PMS_TEST_DEVICE_CAP=<k> caps the reservation (tests of the rerun path).
@@ -323,6 +326,8 @@ struct Ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     DevBuf d_raw, d_win, d_out, d_meta, d_gq;
     HostBuf h_raw, h_meta, h_back, h_out;
+    DevBuf d_gtab, d_gather;   // batch copy-back: gather table and compacted codes
+    HostBuf h_gtab;
     pms_config cfg = default_config();
     pms_stats last{};
     bool last_pending = false;     // last stats still need the event times
@@ -842,10 +847,34 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
         seg[i + 1] = seg[i] + (status[i] == PMS_OK && caps[i] > 0 ? counts[i] : 0);
     PMS_TRY(c.h_out.ensure(std::max<size_t>(seg[m] * 4, 256)));
     uint32_t* const h_codes = c.h_out.as<uint32_t>();
-    for (size_t i = 0; i < m; ++i)
-        if (status[i] == PMS_OK && caps[i] > 0 && counts[i] && counts[i] <= b.out_cap[i])
-            PMS_HIP(hipMemcpyAsync(h_codes + seg[i], c.d_out.as<uint32_t>() + b.out_off[i],
-                                   counts[i] * 4, hipMemcpyDeviceToHost, c.stream));
+    auto takes = [&](size_t i) {
+        return status[i] == PMS_OK && caps[i] > 0 && counts[i] && counts[i] <= b.out_cap[i];
+    };
+    if (m > kGatherMin) {
+        // Many instances: the device packs their codes into one array
+        // (pms_gather_kernel) and one copy brings it back.
+        PMS_TRY(c.h_gtab.ensure(m * 3 * sizeof(uint64_t)));
+        PMS_TRY(c.d_gtab.ensure(m * 3 * sizeof(uint64_t)));
+        PMS_TRY(c.d_gather.ensure(std::max<size_t>(seg[m] * 4, 256)));
+        uint64_t* const tab = c.h_gtab.as<uint64_t>();
+        for (size_t i = 0; i < m; ++i) {
+            tab[3 * i] = b.out_off[i];
+            tab[3 * i + 1] = seg[i];
+            tab[3 * i + 2] = takes(i) ? counts[i] : 0;
+        }
+        PMS_HIP(hipMemcpyAsync(c.d_gtab.p, tab, m * 3 * sizeof(uint64_t), hipMemcpyHostToDevice,
+                               c.stream));
+        PMS_HIP(pms::launch_gather(c.d_out.as<uint32_t>(), c.d_gtab.as<uint64_t>(),
+                                   static_cast<uint32_t>(m), c.d_gather.as<uint32_t>(), c.stream));
+        if (seg[m])
+            PMS_HIP(hipMemcpyAsync(h_codes, c.d_gather.p, seg[m] * 4, hipMemcpyDeviceToHost,
+                                   c.stream));
+    } else {
+        for (size_t i = 0; i < m; ++i)
+            if (takes(i))
+                PMS_HIP(hipMemcpyAsync(h_codes + seg[i], c.d_out.as<uint32_t>() + b.out_off[i],
+                                       counts[i] * 4, hipMemcpyDeviceToHost, c.stream));
+    }
     PMS_HIP(hipStreamSynchronize(c.stream));
     for (size_t i : rerun) {
         if (status[i] != PMS_OK) continue;
@@ -1711,12 +1740,14 @@ int pms_shutdown(void) {
     c.bw_next = 0;
     if (c.stream) note(hipStreamDestroy(c.stream), "hipStreamDestroy");
     c.stream = nullptr;
-    for (DevBuf* b : {&c.d_raw, &c.d_win, &c.d_out, &c.d_meta, &c.d_gq, &c.dv_win, &c.dv_meta,
+    for (DevBuf* b : {&c.d_raw, &c.d_win, &c.d_out, &c.d_meta, &c.d_gq, &c.d_gtab, &c.d_gather,
+                      &c.dv_win, &c.dv_meta,
                       &c.dv_gq, &c.bw_dev, &c.nb_m, &c.nb_b, &c.nb_codes, &c.nb_deltas,
                       &c.nb_groups, &c.nb_ne, &c.nb_cand, &c.nb_out, &c.nb_count, &c.nb_tcount,
                       &c.nb_toff, &c.nb_tcur, &c.nb_rec, &c.nb_part})
         note(b->release(), "hipFree");
-    for (HostBuf* b : {&c.h_raw, &c.h_meta, &c.h_back, &c.h_out, &c.hv_meta, &c.hv_back, &c.bw_host})
+    for (HostBuf* b : {&c.h_raw, &c.h_meta, &c.h_back, &c.h_out, &c.h_gtab, &c.hv_meta, &c.hv_back,
+                       &c.bw_host})
         note(b->release(), "hipHostFree");
     c.nb_ball_l = c.nb_ball_d = -1;
     c.nb_ball_size = c.nb_nne = 0;

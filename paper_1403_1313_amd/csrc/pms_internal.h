@@ -40,6 +40,10 @@ hipError_t launch_search(const pms_dev_instance* insts, const pms_work_item* wor
 
 hipError_t launch_fill(uint32_t* p, uint64_t words, uint32_t v, hipStream_t stream);
 
+// Copies, for each i < m, tab[3i+2] codes from src + tab[3i] to dst + tab[3i+1].
+hipError_t launch_gather(const uint32_t* src, const uint64_t* tab, uint32_t m, uint32_t* dst,
+                         hipStream_t stream);
+
 // Neighbourhood-intersection method (pms_nbhd.hip).
 hipError_t launch_nbhd_codes(const uint8_t* seqs, int32_t t, int32_t l, int32_t rows,
                              uint32_t* codes, hipStream_t stream);

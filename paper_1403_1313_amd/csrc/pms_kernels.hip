@@ -402,7 +402,29 @@ extern "C" __global__ void pms_fill_kernel(uint32_t* __restrict__ p, uint64_t wo
         p[i] = v;
 }
 
+// Step a7 for a batch: copies the codes of instance blockIdx.x from its
+// reserved output range to its place in one contiguous array, so that one
+// copy brings every instance's codes to the host.  tab[3i], tab[3i+1],
+// tab[3i+2]: source offset, destination offset, count (in codes).
+extern "C" __global__ void __launch_bounds__(256)
+pms_gather_kernel(const uint32_t* __restrict__ src, const uint64_t* __restrict__ tab, uint32_t m,
+                  uint32_t* __restrict__ dst) {
+    const uint32_t i = blockIdx.x;
+    if (i >= m) return;
+    const uint64_t from = tab[3 * static_cast<uint64_t>(i)];
+    const uint64_t to = tab[3 * static_cast<uint64_t>(i) + 1];
+    const uint64_t k = tab[3 * static_cast<uint64_t>(i) + 2];
+    for (uint64_t j = threadIdx.x; j < k; j += blockDim.x) dst[to + j] = src[from + j];
+}
+
 namespace pms {
+
+hipError_t launch_gather(const uint32_t* src, const uint64_t* tab, uint32_t m, uint32_t* dst,
+                         hipStream_t stream) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(pms_gather_kernel, dim3(m), dim3(256), 0, stream, src, tab, m, dst);
+    return hipGetLastError();
+}
 
 hipError_t launch_windows(const pms_win_job* jobs, int32_t rows, int32_t max_t,
                           const uint8_t* seqs, uint32_t* windows, uint32_t* bad,

@@ -328,6 +328,40 @@ def _row_pointers(seqs):
     return ctypes.addressof(arr), (arr, rows), n, t
 
 
+def _instance_records(instances, caps, outs):
+    """pms_instance records for [(seqs, l, d), ...] with output addresses
+    `outs` and capacities `caps`, and the objects that keep the row pointer
+    arrays they address alive."""
+    m = len(instances)
+    rec = np.zeros(max(m, 1), dtype=_INSTANCE_DT)
+    keep = []
+    if m and all(isinstance(x[0], np.ndarray) and x[0].dtype == np.uint8 and x[0].ndim == 2
+                 and x[0].flags["C_CONTIGUOUS"] and min(x[0].shape) >= 1 for x in instances):
+        # Row pointers of every instance in one array, filled column-wise.
+        arrs = [x[0] for x in instances]
+        ns = np.fromiter((a.shape[0] for a in arrs), dtype=np.int64, count=m)
+        ts = np.fromiter((a.shape[1] for a in arrs), dtype=np.int64, count=m)
+        addrs = np.fromiter((a.__array_interface__["data"][0] for a in arrs), dtype=np.uint64,
+                            count=m)
+        first = np.zeros(m, dtype=np.int64)
+        np.cumsum(ns[:-1], out=first[1:])
+        within = np.arange(int(ns.sum()), dtype=np.int64) - np.repeat(first, ns)
+        ptrs = np.repeat(addrs, ns) + (within * np.repeat(ts, ns)).astype(np.uint64)
+        keep.append((arrs, ptrs))
+        rec["seqs"] = np.uint64(ptrs.ctypes.data) + 8 * first.astype(np.uint64)
+        rec["n"][:m], rec["t"][:m] = ns, ts
+        rec["l"][:m] = np.fromiter((x[1] for x in instances), dtype=np.int32, count=m)
+        rec["d"][:m] = np.fromiter((x[2] for x in instances), dtype=np.int32, count=m)
+        rec["out_motifs"][:m] = np.where(caps > 0, outs, np.uint64(0))
+        rec["capacity"][:m] = caps
+    else:
+        for i, (seqs, l, d) in enumerate(instances):
+            addr, k, n, t = _row_pointers(seqs)
+            keep.append(k)
+            rec[i] = (addr, n, t, l, d, int(outs[i]) if caps[i] else 0, caps[i])
+    return rec, keep
+
+
 def solve_many(instances: Sequence[Tuple[object, int, int]], capacities=None):
     """pms_solve_many over [(seqs, l, d), ...]: (status, [motifs], [Result])."""
     m = len(instances)
@@ -337,12 +371,7 @@ def solve_many(instances: Sequence[Tuple[object, int, int]], capacities=None):
     np.cumsum(np.maximum(caps, 1).astype(np.int64), out=offs[1:])
     pool = _out_buffer(int(offs[m]))
     base = pool.ctypes.data
-    rec = np.zeros(max(m, 1), dtype=_INSTANCE_DT)
-    keep = []
-    for i, (seqs, l, d) in enumerate(instances):
-        addr, k, n, t = _row_pointers(seqs)
-        keep.append(k)
-        rec[i] = (addr, n, t, l, d, base + 4 * int(offs[i]) if caps[i] else 0, caps[i])
+    rec, keep = _instance_records(instances, caps, base + 4 * offs[:m].astype(np.uint64))
     res = (Result * max(m, 1))()
     st = _lib.pms_solve_many(ctypes.cast(rec.ctypes.data, ctypes.POINTER(Instance)), m, res)
     del keep
@@ -401,12 +430,8 @@ def autotune_many(instances: Sequence[Tuple[object, int, int]],
     """pms_autotune_many on [(seqs, l, d), ...]: tunes the launch on the batch
     itself and makes the result the current configuration."""
     m = len(instances)
-    rec = np.zeros(max(m, 1), dtype=_INSTANCE_DT)
-    keep = []
-    for i, (seqs, l, d) in enumerate(instances):
-        addr, k, n, t = _row_pointers(seqs)
-        keep.append(k)
-        rec[i] = (addr, n, t, l, d, 0, 0)
+    rec, keep = _instance_records(instances, np.zeros(m, dtype=np.uint64),
+                                  np.zeros(m, dtype=np.uint64))
     cfg = Config()
     st = _lib.pms_autotune_many(ctypes.cast(rec.ctypes.data, ctypes.POINTER(Instance)), m,
                                 cache_path.encode() if cache_path else None, ctypes.byref(cfg))

@@ -24,6 +24,9 @@ hipError_t launch_search(const pms_dev_instance*, const pms_work_item*, uint32_t
     return hipErrorNotSupported;
 }
 hipError_t launch_fill(uint32_t*, uint64_t, uint32_t, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_gather(const uint32_t*, const uint64_t*, uint32_t, uint32_t*, hipStream_t) {
+    return hipErrorNotSupported;
+}
 hipError_t launch_nbhd_codes(const uint8_t*, int32_t, int32_t, int32_t, uint32_t*, hipStream_t) {
     return hipErrorNotSupported;
 }

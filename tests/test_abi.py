@@ -332,3 +332,27 @@ def test_fill_work_items():
     assert nat.fill_work_items(0, 10, 0, 0, 0, 0) == -1
     assert nat.fill_work_items(0, 10, 64, 0, 0, 5) == -1
     assert nat.fill_work_items(1, 1 << 32, 64, 0, np.zeros(1, dtype=rec).ctypes.data, 1) == -1
+
+
+def test_instance_records_both_paths():
+    """The batched binding's instance records: the column-wise path for
+    (n, t) uint8 arrays gives the same fields and row addresses as writing
+    each record in turn (the path for other row types)."""
+    rng = np.random.default_rng(9)
+    arrays = [rng.integers(65, 70, size=(int(n), int(t)), dtype=np.uint8)
+              for n, t in zip(rng.integers(1, 6, 7), rng.integers(5, 40, 7))]
+    inst = [(a, 4 + i % 3, i % 2) for i, a in enumerate(arrays)]
+    caps = np.array([0, 5, 1, 7, 0, 3, 9], dtype=np.uint64)
+    outs = np.arange(7, dtype=np.uint64) * 64 + (1 << 20)
+    fast, keep_fast = nat._instance_records(inst, caps, outs)
+    slow, keep_slow = nat._instance_records([(list(a), l, d) for a, l, d in inst], caps, outs)
+    for name in ("n", "t", "l", "d", "out_motifs", "capacity"):
+        assert np.array_equal(fast[name], slow[name]), name
+    assert np.all(fast["out_motifs"][caps == 0] == 0)
+    for i, a in enumerate(arrays):
+        ptrs = np.frombuffer((ctypes.c_uint64 * a.shape[0]).from_address(int(fast["seqs"][i])),
+                             dtype=np.uint64)
+        assert np.array_equal(ptrs, a.ctypes.data + np.arange(a.shape[0], dtype=np.uint64) * a.shape[1])
+        rows = (ctypes.c_char_p * a.shape[0]).from_address(int(slow["seqs"][i]))
+        assert list(rows) == [bytes(x) for x in a]
+    del keep_fast, keep_slow
