@@ -91,6 +91,26 @@ def test_solve_many_per_instance_overflow(nat):
             assert res[i].status == nat.PMS_OK and np.array_equal(g, w)
 
 
+def test_solve_many_gather_with_size_queries_and_small_batches(nat):
+    """The batch copy-back: more than four instances go through one device
+    gather, the others through a copy each; size queries (capacity 0) and
+    an overflowing instance sit between instances that return codes, and
+    both ways give the oracle's sets."""
+    batch = mixed_batch()
+    want = oracle_sets(batch)
+    caps = [1 << 16] * len(batch)
+    caps[1] = caps[6] = 0
+    big = max(range(len(batch)), key=lambda i: want[i].size)
+    caps[big] = 2
+    for sub in (list(range(len(batch))), [0, 1, 2], [big, 6, 3, 4]):
+        st, got, res = nat.solve_many([batch[i] for i in sub], capacities=[caps[i] for i in sub])
+        for j, i in enumerate(sub):
+            assert res[j].count == want[i].size, (sub, i)
+            k = min(caps[i], want[i].size)
+            assert np.array_equal(got[j], want[i][:k]), (sub, i)
+            assert res[j].status == (nat.PMS_ERR_OVERFLOW if want[i].size > caps[i] else nat.PMS_OK)
+
+
 def test_autotune_cache_and_results(nat, tmp_path):
     path = str(tmp_path / "tune.json")
     inst = fmgen.gen_fm(9, 2, 12, 300, 4)
