@@ -22,6 +22,13 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// v_writelane_b32: lane `lane` of `old` replaced by the wave-uniform `val`
+// (the LLVM intrinsic, which clang exposes under no builtin name here).  Not
+// written as inline asm: v_writelane reads its SGPR operand early, so it
+// needs wait states after the VALU instruction that wrote it (a ballot's
+// v_cmp), which the compiler inserts for the intrinsic but not around asm.
+__device__ int write_lane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 __device__ __forceinline__ uint64_t uni64(uint64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
     const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));

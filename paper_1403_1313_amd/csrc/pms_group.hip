@@ -98,12 +98,6 @@ __device__ __forceinline__ void count_bits(const uint32_t (&m)[P > 0 ? P : 1],
     for (int k = 0; k < 5; ++k) c[k] = nw[k] ? w[k][0] : 0u;
 }
 
-// v_writelane_b32: lane `lane` of `old` replaced by the wave-uniform `val`
-// (the LLVM intrinsic, which clang exposes under no builtin name here).  Not
-// written as inline asm: v_writelane reads its SGPR operand early, so it
-// needs wait states after the VALU instruction that wrote it (a ballot's
-// v_cmp), which the compiler inserts for the intrinsic but not around asm.
-__device__ int write_lane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
 // A wave-uniform value copied into a VGPR.  VALU instructions that read an
 // SGPR issue at half rate on gfx950; the selection tree below reads these

@@ -215,20 +215,34 @@ pms_windows_kernel(const pms_win_job* __restrict__ jobs, const uint8_t* __restri
         }
     } else {
         // Bit-sliced: word (g, p) bit j is the high bit of base p of window
-        // slot 32g+j, word (g, l+p) the low bit.
-        const int total = stride;  // groups * 2l
-        for (int q = threadIdx.x; q < total; q += blockDim.x) {
-            const int g = q / (2 * l), r = q % (2 * l);
-            const int p = r < l ? r : r - l;
-            const int plane = r < l ? 1 : 0;
-            uint32_t v = 0;
-            for (int j = 0; j < 32; ++j) {
-                int start;
-                bool rc;
-                slot_source(32 * g + j, nw, j0, mask_n, both, nbits, l, start, rc);
-                v |= ((slot_base(packed, start, rc, p, l) >> plane) & 1u) << j;
+        // slot 32g+j, word (g, l+p) the low bit.  Each lane takes one window
+        // slot and builds its code; per base and plane one ballot over the
+        // wavefront's 64 slots gives the words of its two window groups,
+        // which writelane gathers into lanes 0..2l-1 of two registers.
+        const int groups = stride / (2 * l);
+        const int lane = static_cast<int>(threadIdx.x & 63u);
+        const int waves = static_cast<int>(blockDim.x >> 6);
+        for (int g2 = static_cast<int>(threadIdx.x >> 6); 2 * g2 < groups; g2 += waves) {
+            const int w = 64 * g2 + lane;
+            int start;
+            bool rc;
+            slot_source(w, nw, j0, mask_n, both, nbits, l, start, rc);
+            uint32_t code = 0;
+            for (int p = 0; p < l; ++p) code = (code << 2) | slot_base(packed, start, rc, p, l);
+            int lo = 0, hi = 0;
+            for (int p = 0; p < l; ++p) {
+                const int sh = 2 * (l - 1 - p);
+                const uint64_t bh = __builtin_amdgcn_ballot_w64(((code >> (sh + 1)) & 1u) != 0u);
+                const uint64_t bl = __builtin_amdgcn_ballot_w64(((code >> sh) & 1u) != 0u);
+                lo = pms_dev::write_lane(static_cast<int>(static_cast<uint32_t>(bh)), p, lo);
+                hi = pms_dev::write_lane(static_cast<int>(static_cast<uint32_t>(bh >> 32)), p, hi);
+                lo = pms_dev::write_lane(static_cast<int>(static_cast<uint32_t>(bl)), l + p, lo);
+                hi = pms_dev::write_lane(static_cast<int>(static_cast<uint32_t>(bl >> 32)), l + p, hi);
             }
-            dst[q] = v;
+            if (lane < 2 * l) {
+                dst[(2 * g2) * 2 * l + lane] = static_cast<uint32_t>(lo);
+                if (2 * g2 + 1 < groups) dst[(2 * g2 + 1) * 2 * l + lane] = static_cast<uint32_t>(hi);
+            }
         }
     }
 }
