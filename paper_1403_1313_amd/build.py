@@ -23,6 +23,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+# roctx ranges around the entry points (markers for a profiler's trace)
+LIBS = [f"-L{ROCM}/lib", f"-Wl,-rpath,{ROCM}/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def hipcc() -> str:
@@ -45,7 +48,7 @@ def build_id() -> str:
 
 def build(out: str = LIB, extra=(), verbose: bool = False) -> str:
     tmp = out + ".tmp"
-    cmd = [hipcc(), *FLAGS, f'-DPMS_BUILD_ID="{build_id()}"', *extra, *SOURCES, "-o", tmp]
+    cmd = [hipcc(), *FLAGS, f'-DPMS_BUILD_ID="{build_id()}"', *extra, *SOURCES, *LIBS, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)

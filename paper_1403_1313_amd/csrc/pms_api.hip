@@ -26,10 +26,22 @@
 #include <thread>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "pms.h"
 #include "pms_internal.h"
 
 namespace {
+// A roctx range around every entry point that does device work, named after
+// it: a profiler's marker trace (`rocprofv3 --marker-trace`) then shows each
+// call, and each serving step (one pms_step_launch), beside its kernels.
+// Without a profiler attached a range costs a call into the roctx library.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 thread_local std::string g_last_error;
 
@@ -1159,6 +1171,7 @@ int pms_get_config(pms_config* cfg) {
 
 int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t d,
               uint32_t* out_motifs, uint64_t* out_count) {
+    const TraceRange trace_range("pms_solve");
     const auto t_call = std::chrono::steady_clock::now();
     g_last_error.clear();
     if (!out_count) return fail(PMS_ERR_INVALID, "out_count is NULL");
@@ -1182,6 +1195,7 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t 
 
 int pms_solve_ex(const char* const* seqs, int32_t n, const int32_t* lengths, int32_t l,
                  int32_t d, uint32_t flags, uint32_t* out_motifs, uint64_t* out_count) {
+    const TraceRange trace_range("pms_solve_ex");
     const auto t_call = std::chrono::steady_clock::now();
     g_last_error.clear();
     if (!out_count) return fail(PMS_ERR_INVALID, "out_count is NULL");
@@ -1251,6 +1265,7 @@ uint64_t ball_size(int32_t l, int32_t d) {
 
 int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l, int32_t d,
                         uint32_t* out_motifs, uint64_t* out_count) {
+    const TraceRange trace_range("pms_solve_intersect");
     const auto t_call = std::chrono::steady_clock::now();
     g_last_error.clear();
     if (!out_count) return fail(PMS_ERR_INVALID, "out_count is NULL");
@@ -1455,6 +1470,7 @@ int pms_solve_intersect(const char* const* seqs, int32_t n, int32_t t, int32_t l
 }
 
 int pms_solve_many(const pms_instance* inst, int32_t count, pms_result* results) {
+    const TraceRange trace_range("pms_solve_many");
     const auto t_call = std::chrono::steady_clock::now();
     g_last_error.clear();
     if (!inst || !results || count < 0) return fail(PMS_ERR_INVALID, "NULL batch or negative count");
@@ -1546,6 +1562,7 @@ int pms_last_stats(pms_stats* out) {
 
 int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t layout,
                       uint32_t* dev_windows, uint32_t* dev_bad, void* stream) {
+    const TraceRange trace_range("pms_build_windows");
     g_last_error.clear();
     if (!dev_seqs || !dev_windows) return fail(PMS_ERR_INVALID, "NULL device pointer");
     if (n < 1 || n > PMS_MAX_N || l < 1 || l > PMS_MAX_L || t < l || t > PMS_MAX_T)
@@ -1583,6 +1600,7 @@ int pms_build_windows(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, 
 int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32_t max_n,
                     const pms_work_item* dev_work, int32_t n_work, pms_dev_state* dev_state,
                     pms_dev_counters* dev_counters, const pms_config* cfg, void* stream) {
+    const TraceRange trace_range("pms_step_launch");
     g_last_error.clear();
     if (!dev_instances || !dev_state || !dev_counters || (n_work > 0 && !dev_work))
         return fail(PMS_ERR_INVALID, "NULL device pointer");
@@ -1616,6 +1634,7 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
 
 int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
                   uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count, void* stream) {
+    const TraceRange trace_range("pms_solve_dev");
     g_last_error.clear();
     if (!dev_seqs || !dev_count || (capacity > 0 && !dev_out))
         return fail(PMS_ERR_INVALID, "NULL device pointer");
@@ -1708,6 +1727,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
 }
 
 int pms_shutdown(void) {
+    const TraceRange trace_range("pms_shutdown");
     g_last_error.clear();
     std::lock_guard<std::mutex> lk(g_ctx.mu);
     Ctx& c = g_ctx;
@@ -1767,6 +1787,7 @@ int pms_shutdown(void) {
 int pms_solve_dev_noalloc(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int32_t d,
                           uint32_t* dev_out, uint64_t capacity, uint64_t* dev_count,
                           void* stream) {
+    const TraceRange trace_range("pms_solve_dev_noalloc");
     g_last_error.clear();
     if (!dev_seqs || !dev_count || (capacity > 0 && !dev_out))
         return fail(PMS_ERR_INVALID, "NULL device pointer");
@@ -1861,6 +1882,7 @@ int pms_solve_dev_noalloc(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t
 
 int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_path,
                  pms_config* best) {
+    const TraceRange trace_range("pms_autotune");
     g_last_error.clear();
     PMS_TRY(validate_shape(n, t, l, d));
     std::string path = cache_path ? cache_path : "";
@@ -1889,6 +1911,7 @@ int pms_autotune(int32_t n, int32_t t, int32_t l, int32_t d, const char* cache_p
 
 int pms_autotune_many(const pms_instance* inst, int32_t count, const char* cache_path,
                       pms_config* best) {
+    const TraceRange trace_range("pms_autotune_many");
     g_last_error.clear();
     if (!inst || count < 1) return fail(PMS_ERR_INVALID, "NULL batch or count < 1");
     std::vector<Shape> shapes;

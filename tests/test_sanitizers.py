@@ -17,7 +17,8 @@ The same commands by hand::
     hipcc -x hip --cuda-host-only -O1 -g -std=c++17 -Iinclude \\
         -Ipaper_1403_1313_amd/csrc -Xarch_host -fsanitize=address \\
         -Xarch_host -fsanitize=undefined -Xarch_host -fno-sanitize-recover=all \\
-        tests/host/host_checks.cpp -o /tmp/host_checks && /tmp/host_checks /tmp
+        tests/host/host_checks.cpp -o /tmp/host_checks -L/opt/rocm/lib \\
+        -Wl,-rpath,/opt/rocm/lib -lrocprofiler-sdk-roctx && /tmp/host_checks /tmp
 """
 import os
 import shutil
@@ -28,6 +29,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 
 def _gcc_runtime(name):
@@ -71,7 +73,8 @@ def test_host_code_under_asan_ubsan(tmp_path):
            f"-I{os.path.join(ROOT, 'paper_1403_1313_amd', 'csrc')}",
            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
            "-Xarch_host", "-fno-sanitize-recover=all",
-           os.path.join(ROOT, "tests", "host", "host_checks.cpp"), "-o", str(exe)]
+           os.path.join(ROOT, "tests", "host", "host_checks.cpp"), "-o", str(exe),
+           f"-L{ROCM}/lib", f"-Wl,-rpath,{ROCM}/lib", "-lrocprofiler-sdk-roctx"]
     build = subprocess.run(cmd, capture_output=True, text=True)
     assert build.returncode == 0, build.stdout[-2000:] + build.stderr[-4000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
