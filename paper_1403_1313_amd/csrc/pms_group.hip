@@ -512,6 +512,22 @@ __device__ __forceinline__ uint64_t scan_group_shared_any(uint32_t P, cu32* W, u
 // is live here, which keeps the register budget of scan_filtered's loop.
 // Requires 3 <= P <= 13, nb * groups <= 64 and nb <= kFilterBlocks.
 constexpr uint32_t kNoFit = 0xffffffffu;
+
+// Inclusive sum of v over the 64 lanes (every lane active): within each
+// row of 16 lanes, the values 1, 2, 4 and 8 lanes below are added in turn
+// (row_shr; a lane with no such neighbour in its row adds 0), then row 0's
+// total is added to row 1 and row 2's to row 3 (row_bcast:15 on rows 1 and
+// 3), then the total of rows 0-1 to rows 2 and 3 (row_bcast:31 on rows 2
+// and 3).
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xa, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xc, 0xf, false));
+    return v;
+}
 constexpr uint32_t kListWords = 64u;
 constexpr uint32_t kFilterBlocks = 4u;
 
@@ -566,15 +582,12 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
         um |= static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(
             static_cast<int>((b * groups + ln) << 2), static_cast<int>(u[0])));
     um = ln < groups ? um : 0u;
-    // Total and each lane's offset in the list, from the counts' bits.
+    // Total and each lane's offset in the list: an inclusive sum of the
+    // counts over the lanes.
     const uint32_t pc = static_cast<uint32_t>(__builtin_popcount(um));
-    uint32_t total = 0, off = 0;
-#pragma unroll
-    for (int b = 0; b < 6; ++b) {
-        const uint64_t bm = ballot((pc >> b) & 1u);
-        total += static_cast<uint32_t>(__builtin_popcountll(bm)) << b;
-        off += rank_below(bm) << b;
-    }
+    const uint32_t incl = wave_inclusive_sum(pc);
+    const uint32_t total = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(incl), 63));
+    const uint32_t off = incl - pc;
     const uint32_t stride = 12u + 8u * nb;
     const uint32_t dense = (total + 31u) >> 5;
     if (dense * stride + kListWords > PMS_SVT_WORDS) return kNoFit;
@@ -597,7 +610,10 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
         const bool valid = ln < cnt;
         const uint32_t wi = valid ? list[ln] : 0u;
         __builtin_amdgcn_wave_barrier();
-        const uint32_t g = wi >> 5, bit = wi & 31u;
+        const uint32_t g = wi >> 5;
+        // The lane's bit in the words it fetches (none past the list's end),
+        // so that each ballot below is one compare.
+        const uint32_t sel = valid ? 1u << (wi & 31u) : 0u;
         uint32_t lo = 0, hi = 0;
         // Plane words: from lane g (block 0's table lane of window group g).
         uint32_t x[12];
@@ -607,7 +623,7 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
                 __builtin_amdgcn_ds_bpermute(static_cast<int>(g << 2), static_cast<int>(pw[i])));
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
-            const uint64_t bm = ballot(valid && ((x[i] >> bit) & 1u));
+            const uint64_t bm = ballot((x[i] & sel) != 0u);
             lo = static_cast<uint32_t>(write_lane(static_cast<int>(static_cast<uint32_t>(bm)), i,
                                                   static_cast<int>(lo)));
             hi = static_cast<uint32_t>(write_lane(static_cast<int>(static_cast<uint32_t>(bm >> 32)),
@@ -622,7 +638,7 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
                 y[k] = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(src, static_cast<int>(u[k])));
 #pragma unroll
             for (int k = 0; k < 7; ++k) {
-                const uint64_t bm = ballot(valid && ((y[k] >> bit) & 1u));
+                const uint64_t bm = ballot((y[k] & sel) != 0u);
                 const int at = static_cast<int>(12u + 8u * b) + k;
                 lo = static_cast<uint32_t>(write_lane(static_cast<int>(static_cast<uint32_t>(bm)), at,
                                                       static_cast<int>(lo)));
