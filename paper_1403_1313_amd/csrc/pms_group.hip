@@ -500,9 +500,9 @@ __device__ __forceinline__ uint64_t scan_group_shared_any(uint32_t P, cu32* W, u
 // each: the 12 plane words, then U_0..U_6 (and one spare word) per block.
 //  * The union mask of each window group is collected in lane j (one
 //    ds_bpermute per block); the lanes' offsets in the list of passing
-//    windows come from bit-serial ballots of their counts, and each lane
-//    writes the numbers of its passing windows into a 64-entry LDS list,
-//    64 list positions at a time.
+//    windows come from an inclusive sum of their counts over the lanes,
+//    and each lane writes the numbers of its passing windows into a
+//    64-position LDS list, 64 list positions at a time.
 //  * 64 listed windows (or the rest, at the end) are re-sliced: each lane
 //    fetches its window's words from the table lanes (ds_bpermute) and one
 //    ballot per word forms the new bit-sliced words.  Lanes past the listed
@@ -528,7 +528,7 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
     v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xc, 0xf, false));
     return v;
 }
-constexpr uint32_t kListWords = 64u;
+constexpr uint32_t kListWords = 65u;   // 64 list positions and a spare entry
 constexpr uint32_t kFilterBlocks = 4u;
 
 template <int P>
@@ -595,12 +595,16 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
     uint32_t nv = 0;
     for (uint32_t base = 0; base < total; base += 64u) {
         // List positions [base, base + 64): each lane writes its passing
-        // windows' numbers in order.
+        // windows' numbers in order, one per round while some lane has one
+        // left below base + 64; a lane with none in range writes the spare
+        // entry 64 instead, so every round is one store with no branch.
         {
             uint32_t mm = um, at = off;
-            while (mm != 0u && at < base + 64u) {
-                const uint32_t bit = static_cast<uint32_t>(__builtin_ctz(mm));
-                if (at >= base) list[at - base] = 32u * ln + bit;
+            const uint32_t lim = base + 64u;
+            while (ballot(mm != 0u && at < lim) != 0u) {
+                const bool put = mm != 0u && at - base < 64u;
+                const uint32_t bit = static_cast<uint32_t>(__builtin_ffs(static_cast<int>(mm))) - 1u;
+                list[put ? at - base : 64u] = 32u * ln + bit;
                 mm &= mm - 1u;
                 ++at;
             }
@@ -699,17 +703,25 @@ __device__ __forceinline__ uint32_t filter_windows_any(uint32_t P, cu32* W, uint
 
 // Window filter attempt for a group batch (64-candidate kernel): counts the
 // live lanes' blocks of 64 consecutive groups (key = the group's first l - 6
-// bases), and when they are at most `lim` and fit the table lanes, runs
-// filter_windows.  Returns its dense group count (kNoFit otherwise) with the
-// block count and the lane's block.
-__device__ __forceinline__ uint32_t try_filter(uint32_t lim, uint32_t key, bool live, uint32_t P,
-                                               cu32* W, uint32_t groups, int d, uint32_t* svt,
-                                               uint32_t& fblk, uint32_t& fmyb) {
+// bases), and when they are at most `lim` and fit the table lanes (`tab`
+// blocks, 64 / groups), runs filter_windows.  `one`: the batch's block when
+// the caller knows it is a single one (64 consecutive groups from the start
+// of a block), else kNoKey.  Returns the dense group count (kNoFit
+// otherwise) with the block count and the lane's block.
+constexpr uint32_t kNoKey = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t try_filter(uint32_t lim, uint32_t tab, uint32_t one, uint32_t key,
+                                               bool live, uint32_t P, cu32* W, uint32_t groups,
+                                               int d, uint32_t* svt, uint32_t& fblk, uint32_t& fmyb) {
     fblk = 0;
     fmyb = 0;
     if (lim == 0u || P < 3u || groups > 64u) return kNoFit;
     const uint32_t lane = lane_id();
-    const uint32_t kmax = 64u / groups < lim ? 64u / groups : lim;
+    if (one != kNoKey) {
+        fblk = 1;
+        return filter_windows_any(P, W, groups, 1u, one, lane < groups ? lane : 64u, d, svt);
+    }
+    const uint32_t kmax = tab < lim ? tab : lim;
     uint64_t todo = ballot(live);
     for (; todo != 0 && fblk <= kmax; ++fblk) {
         const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
@@ -921,6 +933,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     uint64_t cap = 0;
     uint32_t n = 0, row = 0, groups = 0, P = 0;
     uint32_t fmax = 0;    // window filter: most blocks per batch (0: off)
+    uint32_t tab = 0;     // blocks whose window groups fit the table lanes: 64 / groups
     int d = 0;
 
     for (;;) {
@@ -928,6 +941,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         uint32_t s, prefix = 0;
         Mask alive = 0;
         bool single = false;
+        uint32_t one = kNoKey;   // the batch's block, when it is known to be a single one
         const uint64_t full = ballot((qc & 0xffffu) >= 64u);
         const uint64_t sfull = kSingles ? ballot(qc >= (64u << 16)) : 0;
         if (full | sfull) {
@@ -967,6 +981,8 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             const uint64_t g = next + lane;
             prefix = static_cast<uint32_t>(g);
             alive = g < end ? kAll : static_cast<Mask>(0);
+            if constexpr (S == 3)
+                if ((next & 63u) == 0u) one = static_cast<uint32_t>(next >> 6);
             next += 64;
         } else {
             if (stash == kNone && more) {
@@ -1033,8 +1049,10 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 P = static_cast<uint32_t>(in.l) - S;
                 groups = row / (2u * (P + S));
                 d = in.d;
-                if constexpr (S == 3)
+                if constexpr (S == 3) {
                     fmax = filter && P >= 3u ? uni(filter_block_limit(P - 3u, d)) : 0u;
+                    tab = groups ? uni(64u / groups) : 0u;
+                }
                 pending = 1;
                 next = wi.begin >> (2 * S);
                 end = (wi.begin + wi.len) >> (2 * S);
@@ -1129,26 +1147,26 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             // branch, it cost the general scan registers.)
             bool done = false;
             uint32_t fblk, fmyb;
-            const uint32_t nv = try_filter(fmax, prefix >> 6, alive != 0, P, W + s * row, groups,
-                                           d, svt, fblk, fmyb);
+            const uint32_t nv = try_filter(fmax, tab, one, prefix >> 6, alive != 0, P, W + s * row,
+                                           groups, d, svt, fblk, fmyb);
             if (nv != kNoFit) {
                 pass = scan_filtered(nv, 12u + 8u * fblk, fmyb, svt, prefix & 63u, alive);
                 ++filtered;
                 filtered_groups += nv;
                 done = true;
             } else if (P >= 3u && groups * 12u <= PMS_SVT_WORDS) {
-                const uint32_t kmax = 64u / groups;
                 uint32_t nblk = 0;
-                uint64_t todo = ballot(alive != 0);
-                for (; todo != 0 && nblk <= kmax; ++nblk) {
+                uint64_t todo = one != kNoKey ? 0u : ballot(alive != 0);
+                for (; todo != 0 && nblk <= tab; ++nblk) {
                     const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
                         static_cast<int>(prefix >> 6), static_cast<int>(__builtin_ctzll(todo))));
                     todo &= ~ballot((prefix >> 6) == v);
                 }
-                if (todo == 0 && nblk <= kmax) {
+                if (todo == 0 && nblk <= tab) {
                     const uint32_t hi = prefix >> 6;
-                    uint32_t kv = 0, tj = 64u, myb = 0;
-                    todo = ballot(alive != 0);
+                    uint32_t kv = one != kNoKey ? one : 0u;
+                    uint32_t tj = one != kNoKey && lane < groups ? lane : 64u, myb = 0;
+                    todo = one != kNoKey ? 0u : ballot(alive != 0);
                     for (uint32_t k = 0; todo != 0; ++k) {
                         const uint32_t v = static_cast<uint32_t>(__builtin_amdgcn_readlane(
                             static_cast<int>(hi), static_cast<int>(__builtin_ctzll(todo))));
