@@ -242,14 +242,26 @@ def bench_serving(args):
         same = sum(1 for r, (st, cnt, codes) in zip(results, fifo_codes)
                    if st == nat.PMS_OK and r.count == cnt and np.array_equal(r.motifs, codes))
         # Latency by (l,d): the (15,4) requests set the tail.
+        # Per (l,d) also the medians of the served requests' parts (host
+        # clock, ms), their step counts and their motif counts.
         by_ld = {}
-        for (t_arr, inst), srv_ms, fifo_ms in zip(reqs, lat, fifo_lat):
-            by_ld.setdefault(f"({inst.l},{inst.d})", ([], []))
+        for (t_arr, inst), r, srv_ms, fifo_ms in zip(reqs, results, lat, fifo_lat):
+            by_ld.setdefault(f"({inst.l},{inst.d})", ([], [], []))
             by_ld[f"({inst.l},{inst.d})"][0].append(srv_ms)
             by_ld[f"({inst.l},{inst.d})"][1].append(fifo_ms)
+            by_ld[f"({inst.l},{inst.d})"][2].append(r)
         by_ld = {k: {"requests": len(a), "server_ms_p50": _pct(a, 50), "server_ms_max": max(a),
-                     "fifo_ms_p50": _pct(b, 50), "fifo_ms_max": max(b)}
-                 for k, (a, b) in sorted(by_ld.items())}
+                     "fifo_ms_p50": _pct(b, 50), "fifo_ms_max": max(b),
+                     "server_parts_ms_p50": {
+                         "admit": _pct([1e3 * (r.admitted - r.arrival) for r in c], 50),
+                         "to_first_step": _pct([1e3 * (r.launched - r.admitted) for r in c], 50),
+                         "steps": _pct([1e3 * (r.retired - r.launched) for r in c], 50),
+                         "finish": _pct([1e3 * (r.finished - r.retired) for r in c], 50)},
+                     "steps_mean": float(np.mean([r.steps for r in c])),
+                     "reruns": int(sum(r.reruns for r in c)),
+                     "motifs_p50": _pct([r.count for r in c], 50),
+                     "motifs_max": max(r.count for r in c)}
+                 for k, (a, b, c) in sorted(by_ld.items())}
         out.append({"rate": rate, "requests": count, "solves_per_s": count / span,
                     "latency_ms_p50": _pct(lat, 50), "latency_ms_p99": _pct(lat, 99),
                     "server_stats": stats,

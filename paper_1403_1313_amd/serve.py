@@ -203,10 +203,10 @@ class Server:
     def __init__(self, mem_budget: int = 256 << 20, step_ms: float = 2.0,
                  max_inflight: int = 2, compares_per_s: float = 2.5e14,
                  device: int = 0, config: Optional[dict] = None, reserve: Optional[int] = None,
-                 items_per_step: int = 8192, oldest_share: float = 0.5,
+                 items_per_step: int = 16384, oldest_share: float = 0.5,
                  min_step_ms: Optional[float] = None, backlog_share: float = 0.25,
                  step_timeout_s: float = 60.0, lookahead_ms: float = 0.25,
-                 idle_wait_ms: float = 1.0):
+                 idle_wait_ms: float = 1.0, tail_split: float = 0.125):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)
@@ -225,6 +225,10 @@ class Server:
         self.rate = float(compares_per_s)
         self.step_compares = self.step_s * self.rate
         self.items_per_step = int(items_per_step)
+        # The last tail_split of each request's share of a step goes in items
+        # a quarter of the size, so that a step ends on short items (the
+        # wavefronts then finish together).
+        self.tail_split = float(tail_split)
         self.oldest_share = float(oldest_share)
         self.copy_stream = torch.cuda.Stream(self.dev)
         self.max_inflight = int(max_inflight)
@@ -417,9 +421,9 @@ class Server:
         minimises the mean latency), then the longer requests in arrival
         order; the oldest admitted request is always given half of the step
         so that a long request is never starved by a stream of short ones.
-        Shares are cut into items of about ``step_compares / items_per_step``
-        window compares each, so every step offers a few items per resident
-        wavefront whatever the request sizes are.
+        Shares are cut into items of about 1 / items_per_step of the step's
+        planned window compares each, so every step offers a few items per
+        resident wavefront whatever the request sizes are.
         """
         live = [r for r in self.active if r.cursor < r.total]
         if not live:
@@ -456,13 +460,22 @@ class Server:
             left -= give
         if left > 0:
             shares[oldest.rid] += left
-        item_compares = budget / self.items_per_step
+        # Items sized from the work the step will hold (a lone short request
+        # does not fill the budget): about items_per_step of them in all.
+        planned = sum(min(shares.get(r.rid, 0.0), (r.total - r.cursor) * r.cost_per_cand)
+                      for r in order)
+        item_compares = max(planned, 1.0) / self.items_per_step
         per_req: Dict[int, int] = {}
         used = 0
         table = buf.h_work.data_ptr()
         for r in order:
+            # Shares and items in whole blocks of 4096 candidates (64 groups
+            # of 64) where the request has them, as the library's own work
+            # plan cuts them: every item then starts a block, and a stage-0
+            # batch is one block, which the window filter takes alone.
+            unit = 4096 if r.total >= 4096 else 64
             cands = int(shares.get(r.rid, 0.0) / r.cost_per_cand)
-            cands = max(64, (cands + 63) // 64 * 64)
+            cands = max(unit, (cands + unit - 1) // unit * unit)
             cands = min(cands, r.total - r.cursor)
             if cands <= 0:
                 continue
@@ -470,15 +483,28 @@ class Server:
             if room <= 0:
                 break
             size = int(item_compares / r.cost_per_cand)
-            # A small request is still spread over up to ~1024 items (whole
-            # 64-candidate groups), so that it runs on many wavefronts.
-            size = min(size, max(64, cands // 1024))
-            size = max(64, (size + 63) // 64 * 64)
+            # A small request is still spread over up to ~1024 items, so that
+            # it runs on many wavefronts.
+            size = min(size, max(unit, cands // 1024))
+            size = max(unit, (size + unit - 1) // unit * unit)
+            small = max(unit, (size // 4 + unit - 1) // unit * unit)
+            tail = 0
+            if self.tail_split > 0 and small < size:
+                tail = min(cands, (int(cands * self.tail_split) + small - 1) // small * small)
+            head = cands - tail
             # Items written straight into the pinned table (pms_work_item records).
-            k = nat.fill_work_items(r.cursor, cands, size, r.slot, table + 16 * used, room)
+            k = nat.fill_work_items(r.cursor, head, size, r.slot, table + 16 * used, room) if head else 0
+            if k < 0:
+                continue
+            covered = min(head, k * size)
+            if covered == head and tail and k < room:
+                k2 = nat.fill_work_items(r.cursor + head, tail, small, r.slot,
+                                         table + 16 * (used + k), room - k)
+                if k2 > 0:
+                    k += k2
+                    covered += min(tail, k2 * small)
             if k <= 0:
                 continue
-            covered = min(cands, k * size)
             r.cursor += covered
             buf.compares += float(covered) * r.cost_per_cand
             per_req[r.slot] = k

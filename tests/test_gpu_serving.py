@@ -118,6 +118,43 @@ def test_serving_shapes_rerun_path(env, cases):
         assert srv.stats["reruns"] == sum(rec["count"] > 1000 for _, _, rec in cases)
 
 
+def test_work_items_start_blocks_and_cover_each_request_once(env, cases, monkeypatch):
+    """Every work item the server writes starts a block of 4096 candidates
+    and holds whole blocks (the window filter's single-block batches depend
+    on it; the last item of a request may end at 4^l), and each request's
+    items, over all its steps, cover [0, 4^l) exactly once; the requests are
+    submitted together, so steps hold several of them, and each result equals
+    the oracle's."""
+    nat, serve = env
+    calls = []
+    real = serve.nat.fill_work_items
+
+    def record(begin, count, item_len, inst, out, max_items):
+        k = real(begin, count, item_len, inst, out, max_items)
+        if k > 0:
+            calls.append((inst, begin, min(count, k * item_len), item_len))
+        return k
+
+    monkeypatch.setattr(serve.nat, "fill_work_items", record)
+    announce("work item layout, all requests at once")
+    with serve.Server() as srv:
+        futs = [srv.submit(inst.seqs, spec.l, spec.d) for spec, inst, _ in cases]
+        for (spec, _, rec), f in zip(cases, futs):
+            check(f.result(timeout=300), rec, spec)
+        assert srv.stats["reruns"] == 0
+    # A request's items come in ascending order on its slot; a slot taken
+    # over by a later request starts again at 0.
+    at, ends = {}, []
+    for slot, begin, covered, item_len in calls:
+        assert begin % 4096 == 0 and item_len % 4096 == 0, (slot, begin, item_len)
+        if begin == 0 and at.get(slot, 0) != 0:
+            ends.append(at[slot])
+        assert begin == at.get(slot, 0) or begin == 0, (slot, begin, at.get(slot))   # no gap, no overlap
+        at[slot] = begin + covered
+    ends += list(at.values())
+    assert sorted(ends) == sorted(4 ** spec.l for spec, _, _ in cases)
+
+
 def small_cases():
     """A few quick requests with oracle results computed here."""
     out = []
