@@ -936,6 +936,14 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     uint32_t tab = 0;     // blocks whose window groups fit the table lanes: 64 / groups
     int d = 0;
 
+    // Wave priority: raised for the bookkeeping between scans (queue pops and
+    // pushes, claims, the window filter's phase 1), which is a chain of
+    // dependent LDS, ballot and scalar steps, and lowered for the scans,
+    // which are long runs of independent VALU work.  A wavefront waiting on
+    // its chain then issues as soon as its operands arrive, and the scans of
+    // the other wavefronts on the SIMD fill the issue slots between.
+    constexpr int kPrioChain = 2, kPrioScan = 0;
+    __builtin_amdgcn_s_setprio(kPrioChain);
     for (;;) {
         // prefix: a group's prefix, or a single's motif code.
         uint32_t s, prefix = 0;
@@ -1100,7 +1108,9 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             // two thirds and left the kernel time unchanged: its dependent
             // LDS round trips cost what the scan's instructions did.)
             const bool live = alive != 0;
+            __builtin_amdgcn_s_setprio(kPrioScan);
             const bool ok = live && scan_single_any(P + S, W + s * row, groups, prefix, d);
+            __builtin_amdgcn_s_setprio(kPrioChain);
             visits += live ? 1u : 0u;
             ++batches;
             ++single_batches;
@@ -1150,7 +1160,9 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             const uint32_t nv = try_filter(fmax, tab, one, prefix >> 6, alive != 0, P, W + s * row,
                                            groups, d, svt, fblk, fmyb);
             if (nv != kNoFit) {
+                __builtin_amdgcn_s_setprio(kPrioScan);
                 pass = scan_filtered(nv, 12u + 8u * fblk, fmyb, svt, prefix & 63u, alive);
+                __builtin_amdgcn_s_setprio(kPrioChain);
                 ++filtered;
                 filtered_groups += nv;
                 done = true;
@@ -1179,16 +1191,22 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                             tj = lane - b;
                         }
                     }
+                    __builtin_amdgcn_s_setprio(kPrioScan);
                     pass = scan_group_shared_any(P, W + s * row, groups, kv, tj, myb * groups,
                                                  prefix & 63u, d, alive, svt);
+                    __builtin_amdgcn_s_setprio(kPrioChain);
                     done = true;
                 }
             }
             if (!done) {
+                __builtin_amdgcn_s_setprio(kPrioScan);
                 pass = scan_group_any<S>(P, W + s * row, groups, prefix, d, alive);
+                __builtin_amdgcn_s_setprio(kPrioChain);
             }
         } else {
+            __builtin_amdgcn_s_setprio(kPrioScan);
             pass = scan_group_any<S>(P, W + s * row, groups, prefix, d, alive);
+            __builtin_amdgcn_s_setprio(kPrioChain);
         }
         visits += static_cast<uint32_t>(__builtin_popcountll(static_cast<uint64_t>(alive)));
         ++batches;
