@@ -661,11 +661,13 @@ __device__ __forceinline__ uint32_t filter_windows(cu32* W, uint32_t groups, uin
 }
 
 // The most blocks (up to kFilterBlocks) over which the window filter is
-// expected to keep at most half of the windows, so that it pays for its
-// re-slicing: a random window is within d of a block's Q shared bases with
-// probability p = sum_{k<=d} C(Q,k) 3^k / 4^Q, and of some block's of nb with
-// 1 - (1-p)^nb.  0 when even one block keeps more than half.
-__device__ __forceinline__ uint32_t filter_block_limit(uint32_t Q, int d) {
+// expected to keep at most the fraction `pass_max` of the windows, so that it
+// pays for its re-slicing: a random window is within d of a block's Q shared
+// bases with probability p = sum_{k<=d} C(Q,k) 3^k / 4^Q, and of some block's
+// of nb with 1 - (1-p)^nb.  0 when even one block keeps more.  Group batches
+// take 1/2; single-candidate batches, whose own scan costs about 0.4 of a
+// group scan per window group, take 1/6.
+__device__ __forceinline__ uint32_t filter_block_limit(uint32_t Q, int d, double pass_max) {
     double ball = 0.0, c = 1.0, p3 = 1.0;
     for (uint32_t k = 0; k <= Q && static_cast<int>(k) <= d; ++k) {
         ball += c * p3;
@@ -677,7 +679,7 @@ __device__ __forceinline__ uint32_t filter_block_limit(uint32_t Q, int d) {
     uint32_t nb = 0;
     for (uint32_t b = 1; b <= kFilterBlocks; ++b) {
         r *= keep;
-        if (r >= 0.5) nb = b;
+        if (r >= 1.0 - pass_max) nb = b;
     }
     return nb;
 }
@@ -818,6 +820,56 @@ __device__ __forceinline__ uint64_t scan_filtered(uint32_t nv, uint32_t stride, 
     return group_pass<S>(found, top) & alive;
 }
 
+// Scan of the nv dense window groups filter_windows left in `svt` for the
+// lane's single candidate: myb = its block in the batch, low6 = its last six
+// bases (2 bits each, the first of them most significant).  Per dense group
+// the block's thresholds U_0..U_6 walk through the six unshared positions,
+// U_k <- mismatch ? U_{k+1} : U_k, and what is left, U_0, marks the windows
+// within d of the whole l-mer (33 VALU per dense group).
+__device__ __forceinline__ bool scan_filtered_single(uint32_t nv, uint32_t stride, uint32_t myb,
+                                                     const uint32_t* __restrict__ svt, uint32_t low6) {
+    if (nv == 0) return false;
+    uint32_t ch[6], cl[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const uint32_t b = (low6 >> (2 * (5 - q))) & 3u;
+        ch[q] = 0u - (b >> 1);
+        cl[q] = 0u - (b & 1u);
+    }
+    uint32_t found = 0;
+    const uint4* sp = reinterpret_cast<const uint4*>(svt);
+    const uint32_t ub = (12u + 8u * myb) >> 2;   // the block's thresholds, in uint4 units
+    for (uint32_t g = 0; g < nv; ++g) {
+        const uint32_t at = g * (stride >> 2);
+        uint32_t x[12], v[8];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const uint4 w = sp[at + i];
+            x[4 * i] = w.x;
+            x[4 * i + 1] = w.y;
+            x[4 * i + 2] = w.z;
+            x[4 * i + 3] = w.w;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const uint4 w = sp[at + ub + i];
+            v[4 * i] = w.x;
+            v[4 * i + 1] = w.y;
+            v[4 * i + 2] = w.z;
+            v[4 * i + 3] = w.w;
+        }
+        // x: 0..5 high plane of positions Q..Q+5, 6..11 low plane.
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const uint32_t m = bop3<kOrXor>(x[q] ^ ch[q], x[6 + q], cl[q]);
+#pragma unroll
+            for (int k = 0; k < 6 - q; ++k) v[k] = bop3<kMux>(m, v[k + 1], v[k]);
+        }
+        found |= v[0];
+    }
+    return found != 0u;
+}
+
 // One sequence scan for one candidate per lane: whether some window is
 // within d of the l-mer `code` (motif code).  All L positions are counted
 // per lane by the carry-save tree of scan_group, with no selection tree; the
@@ -933,6 +985,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     uint64_t cap = 0;
     uint32_t n = 0, row = 0, groups = 0, P = 0;
     uint32_t fmax = 0;    // window filter: most blocks per batch (0: off)
+    uint32_t sfmax = 0;   // the same for single-candidate batches
     uint32_t tab = 0;     // blocks whose window groups fit the table lanes: 64 / groups
     int d = 0;
 
@@ -1058,7 +1111,8 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 groups = row / (2u * (P + S));
                 d = in.d;
                 if constexpr (S == 3) {
-                    fmax = filter && P >= 3u ? uni(filter_block_limit(P - 3u, d)) : 0u;
+                    fmax = filter && P >= 3u ? uni(filter_block_limit(P - 3u, d, 0.5)) : 0u;
+                    sfmax = filter && P >= 3u ? uni(filter_block_limit(P - 3u, d, 1.0 / 6.0)) : 0u;
                     tab = groups ? uni(64u / groups) : 0u;
                 }
                 pending = 1;
@@ -1102,14 +1156,20 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
         }
 
         if (kSingles && single) {
-            // One sequence scan for up to 64 single candidates.  (The window
-            // filter, which single batches of up to three blocks of 4096
-            // candidates could use as well, took their VALU count down by
-            // two thirds and left the kernel time unchanged: its dependent
-            // LDS round trips cost what the scan's instructions did.)
+            // One sequence scan for up to 64 single candidates: through the
+            // window filter when their codes fall into at most sfmax blocks
+            // of 4096 candidates (block key: the first l - 6 bases), else
+            // every window.
             const bool live = alive != 0;
+            uint32_t fblk, fmyb;
+            const uint32_t nv = try_filter(sfmax, tab, kNoKey, prefix >> 12, live, P, W + s * row,
+                                           groups, d, svt, fblk, fmyb);
+            bool ok;
             __builtin_amdgcn_s_setprio(kPrioScan);
-            const bool ok = live && scan_single_any(P + S, W + s * row, groups, prefix, d);
+            if (nv != kNoFit)
+                ok = live && scan_filtered_single(nv, 12u + 8u * fblk, fmyb, svt, prefix & 0xfffu);
+            else
+                ok = live && scan_single_any(P + S, W + s * row, groups, prefix, d);
             __builtin_amdgcn_s_setprio(kPrioChain);
             visits += live ? 1u : 0u;
             ++batches;
