@@ -325,7 +325,6 @@ def bench_plain(args):
         "filter": args.filter,
         "filtered_batches": st["filtered_batches"],
         "filtered_dense_groups": st["filtered_groups"],
-        "filtered_single_batches": st["filtered_singles"],
         "slot_efficiency": st["seq_visits"] / max(1, st["candidate_slots"]),
         "variant": nat.VARIANT_NAMES[st["variant"]],
         "motifs": int(codes.size),

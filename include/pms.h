@@ -285,7 +285,6 @@ typedef struct {
                                   (pms_filter); the rest of those batches' windows
                                   were skipped */
     uint64_t filtered_groups;  /* dense 32-window groups the filtered scans ran */
-    uint64_t filtered_singles; /* of `single_batches`: scans through the window filter */
 } pms_stats;
 
 int pms_last_stats(pms_stats* out);
@@ -392,7 +391,6 @@ typedef struct {
     uint64_t single_batches; /* of those, scans of one candidate per lane (GROUP64) */
     uint64_t filtered_batches; /* of those, group scans through the window filter */
     uint64_t filtered_groups;  /* dense 32-window groups those scans ran */
-    uint64_t filtered_singles; /* of single_batches, scans through the window filter */
 } pms_dev_counters;
 
 /*

@@ -157,7 +157,6 @@ def bench_batched(args, emit=True):
         "per_ld_alone": per_ld,
         "filtered_batches": eager["filtered_batches"],
         "filtered_dense_groups": eager["filtered_groups"],
-        "filtered_single_batches": eager["filtered_singles"],
         "batches": eager["batches"], "single_batches": eager["single_batches"],
     }
     nat.set_config(reset=True)

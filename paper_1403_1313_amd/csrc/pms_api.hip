@@ -847,7 +847,6 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     c.last.single_batches = ctr->single_batches;
     c.last.filtered_batches = ctr->filtered_batches;
     c.last.filtered_groups = ctr->filtered_groups;
-    c.last.filtered_singles = ctr->filtered_singles;
     c.last.candidate_slots = candidate_slots(*ctr, b.variant);
     c.last.reruns = 0;
     // Step a7.  Every instance's codes go to its segment of one pinned
@@ -1553,7 +1552,6 @@ int pms_last_stats(pms_stats* out) {
             c.last.single_batches = ctr.single_batches;
             c.last.filtered_batches = ctr.filtered_batches;
             c.last.filtered_groups = ctr.filtered_groups;
-            c.last.filtered_singles = ctr.filtered_singles;
             c.last.candidate_slots = candidate_slots(ctr, c.dv_variant);
         }
         c.last_pending = false;

@@ -975,7 +975,6 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     bool more = true;
     uint64_t next = 0, end = 0;     // group numbers
     uint64_t batches = 0, single_batches = 0, filtered = 0, filtered_groups = 0;
-    uint64_t filtered_singles = 0;
     uint64_t visits = 0;            // per lane
     uint32_t nob = 0;
     // Lane s: groups queued for stage s (low 16 bits) and singles (high 16).
@@ -1172,7 +1171,6 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             else
                 ok = live && scan_single_any(P + S, W + s * row, groups, prefix, d);
             __builtin_amdgcn_s_setprio(kPrioChain);
-            filtered_singles += nv != kNoFit ? 1u : 0u;
             visits += live ? 1u : 0u;
             ++batches;
             ++single_batches;
@@ -1400,9 +1398,6 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->filtered_groups),
                       static_cast<unsigned long long>(filtered_groups));
         }
-        if (filtered_singles)
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->filtered_singles),
-                      static_cast<unsigned long long>(filtered_singles));
     }
 }
 

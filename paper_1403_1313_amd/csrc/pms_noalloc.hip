@@ -58,7 +58,6 @@ pms_noalloc_setup_kernel(uint8_t* __restrict__ base, pms::NoallocLayout lay, uin
         ctr->single_batches = 0;
         ctr->filtered_batches = 0;
         ctr->filtered_groups = 0;
-        ctr->filtered_singles = 0;
         *reinterpret_cast<uint32_t*>(base + lay.off_bad) = 0;
     }
     for (uint32_t i = tid; i < span; i += gridDim.x * blockDim.x) {

@@ -87,7 +87,7 @@ class Stats(ctypes.Structure):
                 ("variant", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("host_prep_ms", ctypes.c_double), ("host_finish_ms", ctypes.c_double),
                 ("single_batches", ctypes.c_uint64), ("filtered_batches", ctypes.c_uint64),
-                ("filtered_groups", ctypes.c_uint64), ("filtered_singles", ctypes.c_uint64)]
+                ("filtered_groups", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))
@@ -119,7 +119,7 @@ class DevCounters(ctypes.Structure):
     _fields_ = [("next_item", ctypes.c_uint32), ("error", ctypes.c_uint32),
                 ("batches", ctypes.c_uint64), ("t_start", ctypes.c_uint64),
                 ("single_batches", ctypes.c_uint64), ("filtered_batches", ctypes.c_uint64),
-                ("filtered_groups", ctypes.c_uint64), ("filtered_singles", ctypes.c_uint64)]
+                ("filtered_groups", ctypes.c_uint64)]
 
 
 def _load():

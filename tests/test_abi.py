@@ -40,12 +40,12 @@ def test_struct_layouts_match_header(tmp_path):
         "pms_stats": ["kernel_ms", "windows_ms", "seq_visits", "batches", "window_compares",
                       "candidate_slots", "grid", "wg_waves", "chunk", "reruns", "variant",
                       "host_prep_ms", "host_finish_ms", "single_batches", "filtered_batches",
-                      "filtered_groups", "filtered_singles"],
+                      "filtered_groups"],
         "pms_dev_instance": ["windows", "out", "out_cap", "n", "nw_stride", "l", "d"],
         "pms_work_item": ["begin", "len", "inst"],
         "pms_dev_state": ["count", "visits", "t_done", "items_left"],
         "pms_dev_counters": ["next_item", "error", "batches", "t_start", "single_batches",
-                             "filtered_batches", "filtered_groups", "filtered_singles"],
+                             "filtered_batches", "filtered_groups"],
         "pms_probe_result": ["lane_ops_per_s", "ms", "sclk_mhz", "lane_ops_per_clk_per_cu",
                              "compute_units"],
     }

@@ -9,9 +9,7 @@ l-6 bases, re-sliced into dense 32-window groups of 12 + 8 x blocks LDS
 words each beside a 64-entry list of the windows that pass (at most 22
 dense groups for one block); rows of more than 64 window groups, batches
 over more blocks, and batches that would need more dense groups than fit
-scan every window.  Batches of single candidates take the filter under a
-stricter rule (at most a sixth of the windows kept), which the long-motif
-cases check through the kernel's count of them.  The cases straddle those limits (G = 1, 2, 19, 22/23,
+scan every window.  The cases straddle those limits (G = 1, 2, 19, 22/23,
 31, 63/64/65 window groups per row), include shapes where most windows pass
 (l = 6: no shared base, so every window passes and the table overflows from
 23 window groups on) and where almost none pass ((16,2)), and reach deeper
@@ -122,17 +120,6 @@ def test_filter_long_motifs_on_subranges(nat, l, d, t):
     assert np.array_equal(on, off)
     assert s_on["seq_visits"] == s_off["seq_visits"]
     assert s_on["filtered_batches"] >= 4 ** l // 4096
-    # Single-candidate batches go through the filter where at most a sixth
-    # of the windows pass a block's shared bases: l - 6 = 8 shared bases at
-    # d = 4 and more (never (13,4) or (12,3)).  At (15,4) many single
-    # batches fall into three blocks or fewer; at l = 16 survivors are so
-    # rare that a batch of them spans many blocks, so no use is required.
-    assert s_off["filtered_singles"] == 0
-    assert s_on["filtered_singles"] <= s_on["single_batches"]
-    if (l, d) in ((13, 4), (12, 3)):
-        assert s_on["filtered_singles"] == 0
-    if (l, d) == (15, 4):
-        assert s_on["filtered_singles"] > s_on["single_batches"] // 4
     cons = oracle.lmer_to_number(inst.consensus)
     assert cons in set(on.tolist())
     for lo in (max(0, cons - (1 << 15)), 0, 4 ** l - (1 << 16)):
