@@ -974,7 +974,10 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     uint32_t cur = kNone, pending = 0, stash = kNone;
     bool more = true;
     uint64_t next = 0, end = 0;     // group numbers
-    uint64_t batches = 0, single_batches = 0, filtered = 0, filtered_groups = 0;
+    // Launch statistics, one per lane of one register: lane 0 batches, 1
+    // single-candidate batches, 2 filtered group batches, 3 their dense
+    // groups (kept out of the scalar registers, which the loop fills).
+    uint32_t stat = 0;
     uint64_t visits = 0;            // per lane
     uint32_t nob = 0;
     // Lane s: groups queued for stage s (low 16 bits) and singles (high 16).
@@ -1172,8 +1175,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 ok = live && scan_single_any(P + S, W + s * row, groups, prefix, d);
             __builtin_amdgcn_s_setprio(kPrioChain);
             visits += live ? 1u : 0u;
-            ++batches;
-            ++single_batches;
+            stat += lane < 2u ? 1u : 0u;
             const uint64_t pm = ballot(ok);
             if (pm) {
                 const uint32_t rk = rank_below(pm);
@@ -1223,8 +1225,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 __builtin_amdgcn_s_setprio(kPrioScan);
                 pass = scan_filtered(nv, 12u + 8u * fblk, fmyb, svt, prefix & 63u, alive);
                 __builtin_amdgcn_s_setprio(kPrioChain);
-                ++filtered;
-                filtered_groups += nv;
+                stat += lane == 2u ? 1u : (lane == 3u ? nv : 0u);
                 done = true;
             } else if (P >= 3u && groups * 12u <= PMS_SVT_WORDS) {
                 uint32_t nblk = 0;
@@ -1269,7 +1270,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             __builtin_amdgcn_s_setprio(kPrioChain);
         }
         visits += static_cast<uint32_t>(__builtin_popcountll(static_cast<uint64_t>(alive)));
-        ++batches;
+        stat += lane == 0u ? 1u : 0u;
         const bool keep = pass != 0;
         const uint64_t pm = ballot(keep);
         if (pm) {
@@ -1386,18 +1387,11 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             }
         }
     }
-    if (lane == 0) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->batches),
-                  static_cast<unsigned long long>(batches));
-        if (single_batches)
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->single_batches),
-                      static_cast<unsigned long long>(single_batches));
-        if (filtered) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->filtered_batches),
-                      static_cast<unsigned long long>(filtered));
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->filtered_groups),
-                      static_cast<unsigned long long>(filtered_groups));
-        }
+    if (lane < 4u && stat != 0u) {
+        uint64_t* const dst = lane == 0u ? &ctr->batches
+                              : lane == 1u ? &ctr->single_batches
+                              : lane == 2u ? &ctr->filtered_batches : &ctr->filtered_groups;
+        atomicAdd(reinterpret_cast<unsigned long long*>(dst), static_cast<unsigned long long>(stat));
     }
 }
 
