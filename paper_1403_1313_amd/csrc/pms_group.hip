@@ -973,7 +973,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
 
     uint32_t cur = kNone, pending = 0, stash = kNone;
     bool more = true;
-    uint64_t next = 0, end = 0;     // group numbers
+    uint32_t next = 0, end = 0;     // group numbers (below 2^28)
     // Launch statistics, one per lane of one register: lane 0 batches, 1
     // single-candidate batches, 2 filtered group batches, 3 their dense
     // groups (kept out of the scalar registers, which the loop fills).
@@ -983,9 +983,11 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     // Lane s: groups queued for stage s (low 16 bits) and singles (high 16).
     uint32_t qc = 0;
 
+    // The current instance's parameters.  Its output pointer and capacity
+    // are read from its record at each flush of the survivor buffer (rare)
+    // instead: the loop's scalar registers are full, and every one taken
+    // out of them removed spills to vector lanes.
     cu32* W = nullptr;
-    uint32_t* out = nullptr;
-    uint64_t cap = 0;
     uint32_t n = 0, row = 0, groups = 0, P = 0;
     uint32_t fmax = 0;    // window filter: most blocks per batch (0: off)
     uint32_t sfmax = 0;   // the same for single-candidate batches
@@ -1042,7 +1044,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             if (lane == s) qc -= single ? (64u << 16) : 64u;
         } else if (next < end) {
             s = 0;
-            const uint64_t g = next + lane;
+            const uint32_t g = next + lane;
             prefix = static_cast<uint32_t>(g);
             alive = g < end ? kAll : static_cast<Mask>(0);
             if constexpr (S == 3)
@@ -1060,8 +1062,8 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                     const pms_work_item wi = load_uniform(work + item);
                     if (wi.inst == cur) {
                         ++pending;
-                        next = wi.begin >> (2 * S);
-                        end = (wi.begin + wi.len) >> (2 * S);
+                        next = static_cast<uint32_t>(wi.begin >> (2 * S));
+                        end = static_cast<uint32_t>((wi.begin + wi.len) >> (2 * S));
                     } else {
                         stash = item;
                     }
@@ -1078,8 +1080,9 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                             base = atomicAdd(reinterpret_cast<unsigned long long*>(&state[cur].count),
                                              static_cast<unsigned long long>(nob));
                         base = uni64(base);
+                        const pms_dev_instance ci = load_uniform(insts + cur);
                         for (uint32_t i = lane; i < nob; i += 64u)
-                            if (base + i < cap) out[base + i] = ob[i];
+                            if (base + i < ci.out_cap) ci.out[base + i] = ob[i];
                         nob = 0;
                     }
                     // Sum the lanes' visit counts, then one atomic per wavefront.
@@ -1106,8 +1109,6 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                 }
                 cur = wi.inst;
                 W = (cu32*)(in.windows);
-                out = in.out;
-                cap = in.out_cap;
                 n = static_cast<uint32_t>(in.n);
                 row = static_cast<uint32_t>(in.nw_stride);
                 P = static_cast<uint32_t>(in.l) - S;
@@ -1119,8 +1120,8 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                     tab = groups ? uni(64u / groups) : 0u;
                 }
                 pending = 1;
-                next = wi.begin >> (2 * S);
-                end = (wi.begin + wi.len) >> (2 * S);
+                next = static_cast<uint32_t>(wi.begin >> (2 * S));
+                end = static_cast<uint32_t>((wi.begin + wi.len) >> (2 * S));
                 continue;
             }
             // No queue is full and no new work: drain the shallowest queue.
@@ -1199,8 +1200,9 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                             base = atomicAdd(reinterpret_cast<unsigned long long*>(&state[cur].count),
                                              static_cast<unsigned long long>(nob));
                         base = uni64(base);
+                        const pms_dev_instance ci = load_uniform(insts + cur);
                         for (uint32_t i = lane; i < nob; i += 64u)
-                            if (base + i < cap) out[base + i] = ob[i];
+                            if (base + i < ci.out_cap) ci.out[base + i] = ob[i];
                         nob = 0;
                     }
                 }
@@ -1379,8 +1381,9 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
                             base = atomicAdd(reinterpret_cast<unsigned long long*>(&state[cur].count),
                                              static_cast<unsigned long long>(nob));
                         base = uni64(base);
+                        const pms_dev_instance ci = load_uniform(insts + cur);
                         for (uint32_t i = lane; i < nob; i += 64u)
-                            if (base + i < cap) out[base + i] = ob[i];
+                            if (base + i < ci.out_cap) ci.out[base + i] = ob[i];
                         nob = 0;
                     }
                 }
