@@ -27,6 +27,11 @@
 //    exactly as in the per-lane kernel.
 //  * Candidates alive after the last sequence are staged in LDS and flushed
 //    with one global atomicAdd per flush.
+//  * S = 3 only: groups with at most two live members go on as single
+//    candidates (scan_single, 64 singles per wavefront); group and single
+//    batches whose candidates fall into a few blocks of 4096 scan only the
+//    windows within d of the blocks' shared first l - 6 bases (the window
+//    filter: filter_windows, then scan_filtered or scan_filtered_single).
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
