@@ -8,7 +8,9 @@ compared with ``tests/golden/serving.json`` (oracle, skip mode): motif count,
 SHA-256 of the ascending codes and the enhanced rule's visit count, exactly.
 They are served one at a time, all at once, at the stream's own arrival
 times, and with a small first output reservation (so that the large outputs
-take the rerun path).  Failure handling is forced from the host: an injected
+take the rerun path); the server's work items are checked to start blocks
+of 4096 candidates and to cover each request once, and items moved off
+those boundaries still give the oracle's results.  Failure handling is forced from the host: an injected
 launch failure, an injected window-build failure, a step whose kernel
 reports an instance it could not run (the server is told a too small n
 bound), and a step timeout; every kernel still runs to its normal end.
@@ -153,6 +155,42 @@ def test_work_items_start_blocks_and_cover_each_request_once(env, cases, monkeyp
         at[slot] = begin + covered
     ends += list(at.values())
     assert sorted(ends) == sorted(4 ** spec.l for spec, _, _ in cases)
+
+
+def test_unaligned_work_items_match_oracle(env, cases, monkeypatch):
+    """Work items that do not start on blocks of 4096 candidates: each call's
+    interior item boundaries are moved by 17 groups of 64 candidates (the
+    items still cover the same range, once), so stage-0 batches straddle
+    two blocks and take the window filter's block count instead of its
+    single-block path; every result still equals the oracle's."""
+    import ctypes
+    nat, serve = env
+    real = serve.nat.fill_work_items
+    shift = 17 * 64
+    moved = []
+
+    def unaligned(begin, count, item_len, inst, out, max_items):
+        k = real(begin, count, item_len, inst, out, max_items)
+        if k >= 2:
+            recs = (nat.WorkItem * k).from_address(out)
+            end = recs[k - 1].begin + recs[k - 1].len
+            if recs[k - 1].len > shift:
+                for i in range(1, k):
+                    recs[i].begin += shift
+                for i in range(k - 1):
+                    recs[i].len = recs[i + 1].begin - recs[i].begin
+                recs[k - 1].len = end - recs[k - 1].begin
+                assert recs[0].begin == begin and recs[k - 1].begin + recs[k - 1].len == end
+                moved.append(k)
+        return k
+
+    monkeypatch.setattr(serve.nat, "fill_work_items", unaligned)
+    announce("unaligned work items, all requests at once")
+    with serve.Server() as srv:
+        futs = [srv.submit(inst.seqs, spec.l, spec.d) for spec, inst, _ in cases]
+        for (spec, _, rec), f in zip(cases, futs):
+            check(f.result(timeout=300), rec, spec)
+    assert moved
 
 
 def small_cases():
