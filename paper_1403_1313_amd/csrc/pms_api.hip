@@ -524,7 +524,10 @@ ItemPlan item_plan(const Shape& s, double share, const pms_config& cfg, uint64_t
 }
 
 // Cuts each instance's candidate range into work items.  Instances go in
-// descending order of estimated work (longest first).  An instance receives a
+// ascending order of estimated work (shortest first: the wavefronts take
+// items in table order, so short instances complete early instead of
+// behind the long ones; the launch still ends on items of one long
+// instance, which all wavefronts share).  An instance receives a
 // number of items in proportion to its share of the launch's estimated work,
 // about `target_items` in all, and never items smaller than `chunk`
 // candidates; inside an instance the last tail_split/64 of the range uses
@@ -605,7 +608,7 @@ void plan_batch(Batch& b, const pms_config& cfg, uint64_t target_items) {
     }
     std::vector<int> order(m);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] < cost[c]; });
     build_work(b, order, cost, cfg, target_items);
     // Per-call records first (instances, then state, counters and bad-byte
     // flags, which come back after the launch), then the plan's tables
