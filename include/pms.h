@@ -210,8 +210,11 @@ enum pms_filter {
 
 /* Shape of the persistent search launch.  Zero fields mean "default". */
 typedef struct {
-    uint32_t chunk;        /* least candidates per work item (multiple of 64); items are
-                              rounded up to multiples of 4096 candidates for l >= 6 */
+    uint32_t chunk;        /* least candidates per work item (multiple of 64; default
+                              4096); items are rounded up to multiples of 4096 candidates
+                              for l >= 6, and a launch cuts each instance into items in
+                              proportion to its work, about 8 per resident wavefront for
+                              one instance and 32 for a batch */
     uint32_t wg_waves;     /* 64-lane wavefronts per workgroup (1..16) */
     uint32_t wgs_per_cu;   /* resident workgroups per compute unit (0 = as many as fit) */
     uint32_t tail_split;   /* work items of the last tail_split/64 of each instance are

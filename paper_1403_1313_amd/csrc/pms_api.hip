@@ -141,7 +141,7 @@ struct HostBuf {
 // ---------------------------------------------------------------------------
 pms_config default_config() {
     pms_config c;
-    c.chunk = 1u << 14;
+    c.chunk = 1u << 12;   // one block of 4096 candidates at least; target_items sets the rest
     c.wg_waves = 4;
     c.wgs_per_cu = 0;
     c.tail_split = 0;
@@ -390,8 +390,15 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// About 32 work items per wavefront the device can hold resident.
-uint64_t target_items(const Ctx& c) { return static_cast<uint64_t>(std::max(c.cus, 1)) * 16u * 32u; }
+// Work items a launch of `instances` instances is cut into, per wavefront
+// the device can hold resident: about 8 for one instance and 32 for a
+// batch.  Every claim is a device-scope atomic on one counter, and claims
+// of one instance's small items serialize there ((15,4): 131072 items of
+// 8192 candidates 1.63 ms, 65536 of 16384 0.98 ms, 32768 of 32768 0.93 ms);
+// a batch keeps finer items so that its short instances finish early.
+uint64_t target_items(const Ctx& c, size_t instances) {
+    return static_cast<uint64_t>(std::max(c.cus, 1)) * 16u * (instances > 1 ? 32u : 8u);
+}
 
 // Device properties and the address of this device's copy of the fixed
 // scratch (pms_solve_dev_noalloc): no stream, event or memory is created.
@@ -821,7 +828,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
     b.rows = rows;
     b.out_cap.resize(m);
     for (size_t i = 0; i < m; ++i) b.out_cap[i] = caps[i] == 0 ? kCountOnly : 0;
-    plan_batch(b, cfg, target_items(c));
+    plan_batch(b, cfg, target_items(c, m));
     PMS_TRY(stage_batch(c, b));
     const double prep_ms = ms_since(c.t_call);
     PMS_TRY(run_batch(c, b, cfg, use_graph));
@@ -897,7 +904,7 @@ int solve_instances(Ctx& c, const std::vector<Shape>& shapes,
         r.shape = {shapes[i]};
         r.rows = {rows[i]};
         r.out_cap = {counts[i]};
-        plan_batch(r, cfg, target_items(c));
+        plan_batch(r, cfg, target_items(c, 1));
         PMS_TRY(stage_batch(c, r));
         PMS_TRY(run_batch(c, r, cfg, false));
         const pms_dev_state* rs = c.h_back.as<pms_dev_state>(r.off_state);
@@ -1063,7 +1070,7 @@ int tune_grid(Ctx& c, const std::vector<Shape>& shapes,
                     b.shape = shapes;
                     b.rows = rows;
                     b.out_cap.assign(shapes.size(), 0);
-                    plan_batch(b, cfg, target_items(c));
+                    plan_batch(b, cfg, target_items(c, shapes.size()));
                     PMS_TRY(stage_batch(c, b));
                     double ms = 1e300;
                     for (int rep = 0; rep < reps; ++rep) {
@@ -1651,7 +1658,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     std::ostringstream kss;
     kss << n << ':' << t << ':' << l << ':' << d << ':' << cfg.chunk << ':' << cfg.wg_waves << ':'
         << cfg.wgs_per_cu << ':' << cfg.tail_split << ':' << cfg.variant << ':' << cfg.filter << ':'
-        << target_items(c);
+        << target_items(c, 1);
     const std::string key = kss.str();
     const bool reuse = c.dv_plan_valid && key == c.dv_key;
     if (!reuse) {
@@ -1659,7 +1666,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
         c.dv_plan = Batch{};
         c.dv_plan.shape = {Shape{n, t, l, d}};
         c.dv_plan.out_cap = {1};
-        plan_batch(c.dv_plan, cfg, target_items(c));
+        plan_batch(c.dv_plan, cfg, target_items(c, 1));
     }
     const Batch& b = c.dv_plan;
     Shape2 sh;
@@ -1805,7 +1812,7 @@ int pms_solve_dev_noalloc(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t
     const uint32_t variant = choose_variant({shape}, cfg.variant);
     const int32_t layout = variant == PMS_VARIANT_LANE ? PMS_LAYOUT_PLANES : PMS_LAYOUT_BITSLICED;
     // The same items the host planner makes for one instance.
-    const ItemPlan ip = item_plan(shape, 1.0, cfg, target_items(c));
+    const ItemPlan ip = item_plan(shape, 1.0, cfg, target_items(c, 1));
     pms::NoallocLayout lay{};
     lay.n = n;
     lay.t = t;

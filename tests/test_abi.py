@@ -177,7 +177,7 @@ def test_config_validation():
     nat.set_config(chunk=4096, wg_waves=2)
     assert nat.get_config()["chunk"] == 4096 and nat.get_config()["wg_waves"] == 2
     nat.set_config(reset=True)
-    assert nat.get_config() == {"chunk": 16384, "wg_waves": 4, "wgs_per_cu": 0, "tail_split": 0,
+    assert nat.get_config() == {"chunk": 4096, "wg_waves": 4, "wgs_per_cu": 0, "tail_split": 0,
                                 "variant": 0, "filter": 0}
     with pytest.raises(nat.PmsError):
         nat.set_config(variant=4)
