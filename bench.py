@@ -290,7 +290,11 @@ def bench_plain(args):
             parity = [nat.decode(int(c), l) for c in codes] == recs[0]["motifs"] and \
                 st["seq_visits"] == recs[0]["skip_visits"]
 
-    traffic = rec.get("bytes_per_launch") if (rec and fresh) else None
+    # HBM bytes follow the work-item count as well as the kernel (each claim
+    # and its record are traffic), so the stored figure holds only for the
+    # same table size.
+    traffic = rec.get("bytes_per_launch") if (rec and fresh and
+                                               rec.get("work_items") == st["work_items"]) else None
     line = {
         "metric": "candidates/s",
         "value": cands / (ms_step * 1e-3),
@@ -329,7 +333,8 @@ def bench_plain(args):
         "variant": nat.VARIANT_NAMES[st["variant"]],
         "motifs": int(codes.size),
         "parity_vs_golden": parity,
-        "launch": {"grid": st["grid"], "wg_waves": st["wg_waves"], "chunk": st["chunk"]},
+        "launch": {"grid": st["grid"], "wg_waves": st["wg_waves"], "chunk": st["chunk"],
+                   "work_items": st["work_items"]},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,

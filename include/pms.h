@@ -278,7 +278,7 @@ typedef struct {
     uint32_t chunk;
     uint32_t reruns;         /* relaunches caused by device output overflow */
     uint32_t variant;        /* pms_variant actually launched (LANE, GROUP or GROUP64) */
-    uint32_t reserved;
+    uint32_t work_items;     /* work items in the launch's table (the claims it makes) */
     double host_prep_ms;     /* host-level calls: validation, planning and staging before
                                 the launch (0 for device-level calls) */
     double host_finish_ms;   /* host-level calls: copy-back, sort and capacity handling

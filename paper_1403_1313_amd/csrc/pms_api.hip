@@ -766,6 +766,7 @@ int run_batch(Ctx& c, Batch& b, const pms_config& cfg, bool use_graph) {
     c.last.wg_waves = waves;
     c.last.chunk = cfg.chunk;
     c.last.variant = b.variant;
+    c.last.work_items = static_cast<uint32_t>(b.work.size());
     c.last_pending = false;
     return PMS_OK;
 }
@@ -1637,6 +1638,7 @@ int pms_step_launch(const pms_dev_instance* dev_instances, int32_t n_inst, int32
     c.last.wg_waves = waves;
     c.last.chunk = r.chunk;
     c.last.variant = variant;
+    c.last.work_items = static_cast<uint32_t>(n_work);
     c.last_pending = true;
     c.dv_counters = false;
     return PMS_OK;
@@ -1727,6 +1729,7 @@ int pms_solve_dev(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t l, int3
     c.last.wg_waves = waves;
     c.last.chunk = cfg.chunk;
     c.last.variant = b.variant;
+    c.last.work_items = static_cast<uint32_t>(b.work.size());
     c.last_pending = true;
     c.dv_counters = true;
     c.dv_variant = b.variant;
@@ -1885,6 +1888,7 @@ int pms_solve_dev_noalloc(const uint8_t* dev_seqs, int32_t n, int32_t t, int32_t
     c.last.wg_waves = sh.waves;
     c.last.chunk = cfg.chunk;
     c.last.variant = variant;
+    c.last.work_items = lay.n_items;
     c.last_pending = false;
     c.dv_counters = false;
     return PMS_OK;

@@ -84,7 +84,7 @@ class Stats(ctypes.Structure):
                 ("window_compares", ctypes.c_uint64), ("candidate_slots", ctypes.c_uint64),
                 ("grid", ctypes.c_uint32), ("wg_waves", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("reruns", ctypes.c_uint32),
-                ("variant", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("variant", ctypes.c_uint32), ("work_items", ctypes.c_uint32),
                 ("host_prep_ms", ctypes.c_double), ("host_finish_ms", ctypes.c_double),
                 ("single_batches", ctypes.c_uint64), ("filtered_batches", ctypes.c_uint64),
                 ("filtered_groups", ctypes.c_uint64)]

@@ -235,6 +235,8 @@ def test_solve_dev_through_torch(nat):
     assert np.array_equal(codes, want)
     st = nat.last_stats()
     assert st["seq_visits"] == visits and st["kernel_ms"] > 0
+    # Items hold at least one 64-candidate lane block each.
+    assert 1 <= st["work_items"] <= 4 ** 11 // 64
 
 
 def _reference_windows(seqs, l, layout):
