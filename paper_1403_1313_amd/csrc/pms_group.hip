@@ -963,9 +963,9 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
     constexpr uint32_t kEntryWords = 1 + sizeof(Mask) / 4;
     constexpr bool kSingles = S == 3;
     // A group with at most this many live members splits into singles (one
-    // fewer where d >= 4 and the singles' window filter is on: there a
-    // filtered group scan of two members costs less than their two single
-    // scans).  1 or 2 only: the singles push below writes a group's lowest
+    // fewer where d >= 4, the singles' window filter is on and the filter's
+    // table holds two blocks or more: there a filtered group scan of two
+    // members costs less than their two single scans).  1 or 2 only: the singles push below writes a group's lowest
     // and highest live codes, so a third member would be lost.
     constexpr uint32_t kSparse = 2;
     constexpr uint32_t kStageWords = pms::stage_queue_words(S);
@@ -1289,7 +1289,7 @@ __device__ __forceinline__ void search_groups(const pms_dev_instance* __restrict
             if (s + 1 < n) {
                 const uint32_t live = static_cast<uint32_t>(__builtin_popcountll(static_cast<uint64_t>(pass)));
                 const bool sparse = kSingles && keep &&
-                                    live <= kSparse - (d >= 4 && sfmax != 0u ? 1u : 0u);
+                                    live <= kSparse - (d >= 4 && sfmax != 0u && tab >= 2u ? 1u : 0u);
                 const uint64_t dm = kSingles ? ballot(keep && !sparse) : pm;
                 const uint32_t r = s;
                 if (dm) {
